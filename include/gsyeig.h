@@ -1,0 +1,205 @@
+/*
+ * gsyeig.h -- C ABI of the MI355X (gfx950) Krylov solver for the dense
+ * symmetric-definite generalized eigenproblem
+ *
+ *        A X = B X Lambda,   A = A^T,  B = B^T positive definite,      (Eq. 1)
+ *
+ * for the s algebraically smallest (or largest) eigenpairs, s << n, by the
+ * paper's variant KI (Section 2.3, "Krylov-subspace with implicit operation
+ * on C"; Table 1 keys GS1, KI1-KI5, BT1):
+ *
+ *   GS1  B = U^T U, U upper triangular                          (Eq. 2)
+ *   KI1  wbar = U^-1 w          (triangular solve)
+ *   KI2  what = A wbar          (symmetric matrix-vector product)
+ *   KI3  z    = U^-T what       (triangular solve)     -> z = C w, Eq. 3
+ *   KI4  Lanczos update with full re-orthogonalisation ("twice")
+ *   KI5  Ritz values/vectors from the tridiagonal T_m and basis V_m
+ *   BT1  X = U^-1 Y                                            (Eq. 4)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every matrix/vector pointer is a DEVICE pointer (HBM of the GPU that is
+ *   current when the context was created) unless the argument says "host".
+ *   The caller allocates and owns them; the library never frees them.
+ * - Square matrices (A, B, U) are ROW-MAJOR with leading dimension ld >= n:
+ *   element (i, j) is at p[i*ld + j].  A and B are read in full storage.
+ *   U is upper triangular; only its upper triangle (incl. diagonal) is read.
+ * - Blocks of vectors (Y, X, V; n x s) are COLUMN-MAJOR with ld >= n: vector
+ *   j occupies p[j*ld .. j*ld + n-1] (a row-major (s, n) torch tensor).
+ * - All work is enqueued on the context's HIP stream.  Entry points that
+ *   return results on the device are asynchronous unless stated otherwise;
+ *   gsyeig_potrf, gsyeig_lanczos and gsyeig_solve synchronise the stream
+ *   because they must report an info code.
+ * - Return codes (LAPACK style):
+ *      0            success
+ *     -i            argument i (1-based) is illegal (n < 1, s > n, ld < n,
+ *                   NULL pointer, ...); nothing was enqueued
+ *     +k (k <= n)   the leading minor of order k of B is not positive
+ *                   definite (Eq. 2 fails)
+ *     GSYEIG_ENOCONV  fewer than s pairs met the tolerance within max_steps
+ *     GSYEIG_EHIP     a HIP runtime call failed
+ *     GSYEIG_ESPIN    a persistent kernel's bounded wait expired (internal
+ *                     error; outputs undefined, the GPU is left usable)
+ * - Contexts are not thread-safe; use one per host thread/stream.
+ */
+#ifndef GSYEIG_H
+#define GSYEIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSYEIG_ENOCONV 0x40000000
+#define GSYEIG_EHIP 0x40000001
+#define GSYEIG_ESPIN 0x40000002
+#define GSYEIG_ENOMEM 0x40000003
+
+typedef struct gsyeig_ctx gsyeig_ctx;
+
+typedef enum { GSYEIG_FP64 = 0, GSYEIG_MIXED = 1 } gsyeig_prec;
+
+typedef struct {
+    int prec;              /* GSYEIG_FP64 (every step in FP64)                   */
+    int block;             /* Lanczos block size; 1 = single-vector Lanczos       */
+    int which;             /* 0 = s smallest (default), 1 = s largest             */
+    int invert;            /* reserved (0): solve the inverse pencil (B, A)       */
+    double tol;            /* Ritz-residual tolerance relative to ||T_m||          */
+                           /*   (default 1e-12); Section 3.3 used tol = 0, i.e.   */
+                           /*   machine precision, in ARPACK's dsaupd             */
+    int64_t max_steps;     /* cap on operator applications m (default             */
+                           /*   min(n, 100 s + 2000))                             */
+    int64_t check_every;   /* steps between convergence checks (default 25)       */
+    uint64_t seed;         /* start vector w_0 = SplitMix64(seed) in [-1,1)^n     */
+    const double *v0;      /* optional device start vector (n); overrides seed    */
+    int64_t profile_every; /* 0 = off; else time KI1/KI2/KI3 with hipEvents on    */
+                           /*   every profile_every-th Lanczos step (sampled)     */
+} gsyeig_opts;
+
+typedef struct {
+    int64_t steps;         /* Lanczos steps m actually taken                       */
+    int64_t converged;     /* wanted pairs whose Ritz residual met tol             */
+    double eta_max;        /* max_i ||A x_i - l_i B x_i|| / ((||A||F+|l_i| ||B||F)||x_i||) */
+    double rho_f;          /* ||A X - B X L||_F / max(||A||_F, ||B||_F) (Tables 3/7) */
+    double omega;          /* ||I - X^T B X||_F                                    */
+    double normA_f, normB_f;
+    /* wall time of each Table-1 key, milliseconds (hipEvent) */
+    double t_gs1_ms;       /* Cholesky                                             */
+    double t_ki_ms;        /* Lanczos loop: KI1 + KI2 + KI3 + KI4 + checks         */
+    double t_ki5_ms;       /* Ritz vectors                                         */
+    double t_bt1_ms;       /* back-transform                                       */
+    double t_check_ms;     /* FP64 residual/orthogonality check                    */
+    double t_total_ms;
+    /* sampled per-launch kernel times (opts.profile_every > 0), milliseconds  */
+    int64_t prof_samples;  /* number of sampled steps                          */
+    double t_ki1_ms_sum;   /* sum over samples of the U^-1 sweep (KI1)         */
+    double t_ki2_ms_sum;   /* ... of the A product (KI2)                       */
+    double t_ki3_ms_sum;   /* ... of the U^-T sweep (KI3)                      */
+} gsyeig_info;
+
+/* Library version string (host, static storage). */
+const char *gsyeig_version(void);
+
+/* Fill *opts with the defaults listed above.  Returns 0, or -1 if NULL. */
+int gsyeig_opts_default(gsyeig_opts *opts);
+
+/* Create a context bound to `hip_stream` (a hipStream_t, NULL = the null
+ * stream) on the current device.  Allocates a small control block; larger
+ * workspace is grown on demand and owned by the context. */
+int gsyeig_create(gsyeig_ctx **ctx, void *hip_stream);
+
+/* Wait for the context's stream and free everything the context owns. */
+int gsyeig_destroy(gsyeig_ctx *ctx);
+
+/* Bytes of device workspace gsyeig_solve needs for (n, s, opts) (host-only
+ * arithmetic; no GPU call). */
+int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes);
+
+/* GS1 (Eq. 2; Table 1): B = U^T U in place.  On return the upper triangle
+ * (incl. diagonal) of B holds U; the strict lower triangle of B is left
+ * untouched (so it still holds B's lower half).  `U_lowprec` must be NULL
+ * (reserved).  Synchronises; returns 0 or the failing minor k > 0. */
+int gsyeig_potrf(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, const gsyeig_opts *opts,
+                 void *U_lowprec);
+
+/* KI1 / KI3 (Table 1): x = U^-1 b (trans = 0) or x = U^-T b (trans = 1).
+ * x may alias b.  Asynchronous. */
+int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int trans,
+                const double *b, double *x);
+
+/* KI2 (Table 1): y = A x, A symmetric in full storage; only the upper
+ * triangle of A is read.  x and y must not alias.  Asynchronous. */
+int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x,
+                double *y);
+
+/* KI1-KI3: z = U^-T (A (U^-1 w)) = C w, the implicit operator of variant KI
+ * (Section 2.3).  z may alias w.  Asynchronous. */
+int gsyeig_apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
+                    int64_t ldu, const double *w, double *z);
+
+/* KI1-KI4 for exactly k steps (Section 2.3, Lanczos with the three-term
+ * recurrence and classical Gram-Schmidt re-orthogonalisation applied twice):
+ *   w_0 = v0/||v0||; for j < k:  z = C w_j - beta_{j-1} w_{j-1};
+ *   alpha_j = w_j^T z; z -= alpha_j w_j; twice { z -= W_j (W_j^T z) };
+ *   beta_j = ||z||; w_{j+1} = z / beta_j.
+ * alpha, beta: device (k).  V: device n x (k+1) column-major basis, ldv >= n.
+ * v0: device start vector (n).  Asynchronous. */
+int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, int64_t lda,
+                       const double *U, int64_t ldu, const double *v0, double *alpha,
+                       double *beta, double *V, int64_t ldv);
+
+/* KI5, eigen-part (Section 2.3: "obtaining the eigenpairs from T_m, V_m"):
+ * the nwant smallest (which = 0) or largest (which = 1) eigenvalues of the
+ * symmetric tridiagonal T_m (diagonal alpha[0..m-1], off-diagonal
+ * beta[0..m-2]) by Sturm-count bisection, ascending, into theta (device,
+ * nwant); and, if S != NULL, the matching orthonormal eigenvectors by
+ * inverse iteration (re-orthogonalised inside clusters) into S (device,
+ * m x nwant column-major, lds >= m).  Asynchronous. */
+int gsyeig_tridiag_eig(gsyeig_ctx *ctx, int64_t m, const double *alpha, const double *beta,
+                       int64_t nwant, int which, double *theta, double *S, int64_t lds);
+
+/* KI1-KI5: Lanczos on C = U^-T A U^-1 until the s wanted Ritz pairs have
+ * Ritz residual estimate beta_m |e_m^T s_i| <= tol ||T_m|| (checked every
+ * check_every steps) or max_steps is reached.  Returns the Ritz values
+ * (theta, device, s, ascending) and Ritz vectors Y = V_m S (device, n x s
+ * column-major).  U is the upper Cholesky factor (row-major).
+ * *steps_out (host, may be NULL) receives m.  Synchronises.
+ * Returns 0 or GSYEIG_ENOCONV (results are the best available). */
+int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                   const double *U, int64_t ldu, const gsyeig_opts *opts, double *theta,
+                   double *Y, int64_t ldy, int64_t *steps_out);
+
+/* BT1 (Eq. 4; Table 1): X = U^-1 Y in place for s column vectors (n x s
+ * column-major, ldy >= n).  Asynchronous. */
+int gsyeig_backsolve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *U, int64_t ldu,
+                     double *Y_to_X, int64_t ldy);
+
+/* FP64 accuracy check of s pairs (Tables 3/7 metrics + per-pair backward
+ * error).  B is read in full storage if Bdiag == NULL; otherwise only B's
+ * strict LOWER triangle is read and Bdiag (device, n) supplies its diagonal
+ * (the state gsyeig_potrf leaves B in, with the diagonal saved beforehand).
+ * Results go to *out (host): eta_max, rho_f, omega, normA_f, normB_f.
+ * Synchronises. */
+int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, const double *Bdiag, const double *Lambda,
+                 const double *X, int64_t ldx, gsyeig_info *out);
+
+/* The whole path GS1 -> KI1..KI5 -> BT1 -> check (Eq. 1-4).
+ * B is overwritten by U in its upper triangle (Section 2.1: the factor
+ * overwrites B); its strict lower triangle is preserved.  Lambda (device, s)
+ * receives the eigenvalues ascending; X (device, n x s column-major,
+ * ldx >= n) the B-orthonormal eigenvectors, each signed so that its entry
+ * of largest magnitude (lowest index on ties) is positive.  *info (host,
+ * may be NULL) receives steps, timings and the check.  Synchronises.
+ * Returns 0, +k (B not SPD), GSYEIG_ENOCONV, or an error. */
+int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
+                 int64_t ldb, const gsyeig_opts *opts, double *Lambda, double *X, int64_t ldx,
+                 gsyeig_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSYEIG_H */

@@ -1,0 +1,247 @@
+"""Python binding of libgsyeig (MI355X / gfx950 Krylov solver for A X = B X Lambda).
+
+The functions named ``gsyeig_*`` mirror the C ABI in ``include/gsyeig.h``
+argument for argument; device pointers may be passed as integers or as torch
+tensors (their ``data_ptr()`` is used).  They only marshal arguments: every
+step of the computation runs in the HIP library.  The binding refuses to work
+without the built library -- there is no CPU fallback.
+
+``Solver`` is a small convenience layer over the same calls for torch users.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsyeig.so")
+
+GSYEIG_FP64 = 0
+GSYEIG_MIXED = 1
+GSYEIG_ENOCONV = 0x40000000
+GSYEIG_EHIP = 0x40000001
+GSYEIG_ESPIN = 0x40000002
+GSYEIG_ENOMEM = 0x40000003
+
+# every entry point declared in include/gsyeig.h
+EXPORTS = (
+    "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
+    "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
+    "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
+    "gsyeig_check", "gsyeig_solve",
+)
+
+
+class GsyeigError(RuntimeError):
+    def __init__(self, fn, rc):
+        super().__init__(f"{fn} returned {rc} ({_describe(rc)})")
+        self.rc = rc
+
+
+def _describe(rc: int) -> str:
+    if rc == 0:
+        return "success"
+    if rc < 0:
+        return f"illegal argument {-rc}"
+    return {GSYEIG_ENOCONV: "not converged", GSYEIG_EHIP: "HIP error",
+            GSYEIG_ESPIN: "persistent-kernel wait expired", GSYEIG_ENOMEM: "out of device memory"}.get(
+        rc, f"leading minor {rc} of B not positive definite")
+
+
+class gsyeig_opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("block", ctypes.c_int), ("which", ctypes.c_int),
+                ("invert", ctypes.c_int), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("check_every", ctypes.c_int64), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
+                ("profile_every", ctypes.c_int64)]
+
+
+class gsyeig_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("converged", ctypes.c_int64)] + [
+        (k, ctypes.c_double) for k in ("eta_max", "rho_f", "omega", "normA_f", "normB_f", "t_gs1_ms",
+                                       "t_ki_ms", "t_ki5_ms", "t_bt1_ms", "t_check_ms", "t_total_ms")] + [
+        ("prof_samples", ctypes.c_int64), ("t_ki1_ms_sum", ctypes.c_double),
+        ("t_ki2_ms_sum", ctypes.c_double), ("t_ki3_ms_sum", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libgsyeig.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1111_6374_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        sig = {
+            "gsyeig_version": ([], ctypes.c_char_p),
+            "gsyeig_opts_default": ([ctypes.POINTER(gsyeig_opts)], I),
+            "gsyeig_create": ([ctypes.POINTER(P), P], I),
+            "gsyeig_destroy": ([P], I),
+            "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
+            "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
+            "gsyeig_trsv": ([P, I64, P, I64, I, P, P], I),
+            "gsyeig_symv": ([P, I64, P, I64, P, P], I),
+            "gsyeig_apply_op": ([P, I64, P, I64, P, I64, P, P], I),
+            "gsyeig_lanczos_run": ([P, I64, I64, P, I64, P, I64, P, P, P, P, I64], I),
+            "gsyeig_tridiag_eig": ([P, I64, P, P, I64, I, P, P, I64], I),
+            "gsyeig_lanczos": ([P, I64, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, P, I64,
+                                ctypes.POINTER(I64)], I),
+            "gsyeig_backsolve": ([P, I64, I64, P, I64, P, I64], I),
+            "gsyeig_check": ([P, I64, I64, P, I64, P, I64, P, P, P, I64, ctypes.POINTER(gsyeig_info)], I),
+            "gsyeig_solve": ([P, I64, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, P, I64,
+                              ctypes.POINTER(gsyeig_info)], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _p(x):
+    """Device pointer of a tensor (checked FP64 on a GPU) or an int/None."""
+    if x is None or isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda:
+            raise ValueError("gsyeig expects device tensors")
+        return x.data_ptr()
+    raise TypeError(type(x))
+
+
+# ------------------------------------------------------------------ C ABI mirrors
+def gsyeig_version() -> str:
+    return lib().gsyeig_version().decode()
+
+
+def gsyeig_opts_default() -> gsyeig_opts:
+    o = gsyeig_opts()
+    lib().gsyeig_opts_default(ctypes.byref(o))
+    return o
+
+
+def gsyeig_create(hip_stream=None):
+    """Returns (rc, ctx)."""
+    ctx = ctypes.c_void_p()
+    rc = lib().gsyeig_create(ctypes.byref(ctx), hip_stream)
+    return rc, ctx
+
+
+def gsyeig_destroy(ctx) -> int:
+    return lib().gsyeig_destroy(ctx)
+
+
+def gsyeig_workspace_size(n, s, opts=None):
+    """Returns (rc, bytes)."""
+    b = ctypes.c_size_t()
+    rc = lib().gsyeig_workspace_size(n, s, ctypes.byref(opts) if opts else None, ctypes.byref(b))
+    return rc, b.value
+
+
+def gsyeig_potrf(ctx, n, B, ldb, opts=None, U_lowprec=None) -> int:
+    return lib().gsyeig_potrf(ctx, n, _p(B), ldb, ctypes.byref(opts) if opts else None, _p(U_lowprec))
+
+
+def gsyeig_trsv(ctx, n, U, ldu, trans, b, x) -> int:
+    return lib().gsyeig_trsv(ctx, n, _p(U), ldu, trans, _p(b), _p(x))
+
+
+def gsyeig_symv(ctx, n, A, lda, x, y) -> int:
+    return lib().gsyeig_symv(ctx, n, _p(A), lda, _p(x), _p(y))
+
+
+def gsyeig_apply_op(ctx, n, A, lda, U, ldu, w, z) -> int:
+    return lib().gsyeig_apply_op(ctx, n, _p(A), lda, _p(U), ldu, _p(w), _p(z))
+
+
+def gsyeig_lanczos_run(ctx, n, k, A, lda, U, ldu, v0, alpha, beta, V, ldv) -> int:
+    return lib().gsyeig_lanczos_run(ctx, n, k, _p(A), lda, _p(U), ldu, _p(v0), _p(alpha), _p(beta),
+                                    _p(V), ldv)
+
+
+def gsyeig_tridiag_eig(ctx, m, alpha, beta, nwant, which, theta, S=None, lds=0) -> int:
+    return lib().gsyeig_tridiag_eig(ctx, m, _p(alpha), _p(beta), nwant, which, _p(theta), _p(S), lds)
+
+
+def gsyeig_lanczos(ctx, n, s, A, lda, U, ldu, opts, theta, Y, ldy):
+    """Returns (rc, steps)."""
+    steps = ctypes.c_int64()
+    rc = lib().gsyeig_lanczos(ctx, n, s, _p(A), lda, _p(U), ldu, ctypes.byref(opts) if opts else None,
+                              _p(theta), _p(Y), ldy, ctypes.byref(steps))
+    return rc, steps.value
+
+
+def gsyeig_backsolve(ctx, n, s, U, ldu, Y_to_X, ldy) -> int:
+    return lib().gsyeig_backsolve(ctx, n, s, _p(U), ldu, _p(Y_to_X), ldy)
+
+
+def gsyeig_check(ctx, n, s, A, lda, B, ldb, Bdiag, Lambda, X, ldx):
+    """Returns (rc, gsyeig_info with eta_max, rho_f, omega, normA_f, normB_f)."""
+    info = gsyeig_info()
+    rc = lib().gsyeig_check(ctx, n, s, _p(A), lda, _p(B), ldb, _p(Bdiag), _p(Lambda), _p(X), ldx,
+                            ctypes.byref(info))
+    return rc, info
+
+
+def gsyeig_solve(ctx, n, s, A, lda, B, ldb, opts, Lambda, X, ldx):
+    """Returns (rc, gsyeig_info)."""
+    info = gsyeig_info()
+    rc = lib().gsyeig_solve(ctx, n, s, _p(A), lda, _p(B), ldb, ctypes.byref(opts) if opts else None,
+                            _p(Lambda), _p(X), ldx, ctypes.byref(info))
+    return rc, info
+
+
+# ------------------------------------------------------------------ torch convenience
+class Solver:
+    """One context on the current torch stream.  Tensors are FP64 on the GPU;
+    square matrices row-major (torch default), vector blocks as (s, n)
+    tensors (row i = vector i, i.e. column-major n x s)."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        rc, self.ctx = gsyeig_create(stream.cuda_stream)
+        if rc:
+            raise GsyeigError("gsyeig_create", rc)
+
+    def close(self):
+        if self.ctx:
+            gsyeig_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, A, B, s, opts=None, overwrite_b=False):
+        """Lambda (s,), X (s, n), info dict.  B is copied unless overwrite_b."""
+        import torch
+
+        n = A.shape[0]
+        if not overwrite_b:
+            B = B.clone()
+        Lam = torch.empty(s, dtype=torch.float64, device=A.device)
+        X = torch.empty(s, n, dtype=torch.float64, device=A.device)
+        rc, info = gsyeig_solve(self.ctx, n, s, A, A.stride(0), B, B.stride(0), opts, Lam, X, X.stride(0))
+        if rc and rc != GSYEIG_ENOCONV:
+            raise GsyeigError("gsyeig_solve", rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return Lam, X, d

@@ -1,0 +1,683 @@
+// gsyeig_api.hip -- host driver and C ABI (see include/gsyeig.h).
+//
+// The driver only sequences kernels on the context's stream and moves a few
+// scalars (info codes, the converged count, check results) to the host.
+// Every arithmetic step of the path runs in the kernels of this library.
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+// ------------------------------------------------------------------ workspace
+int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out)
+{
+    if (bytes == 0) bytes = 256;
+    if (ctx->ws_bytes[slot] >= bytes) {
+        *out = ctx->ws[slot];
+        return 0;
+    }
+    if (ctx->ws[slot]) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        HIP_TRY(hipFree(ctx->ws[slot]));
+        ctx->ws[slot] = nullptr;
+        ctx->ws_bytes[slot] = 0;
+        if (slot == WS_SYMVMAP) ctx->symv_map_n = -1;
+    }
+    const size_t sz = (bytes + 4095) & ~(size_t)4095;
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return GSYEIG_ENOMEM;
+    }
+    ctx->ws[slot] = p;
+    ctx->ws_bytes[slot] = sz;
+    *out = p;
+    return 0;
+}
+
+static size_t ctl_bytes(int64_t rows) { return PCTL_STAGE_OFFSET + sizeof(double) * (size_t)rows; }
+
+// zero counters, staging entries all STAGE_SENTINEL (all-ones bytes)
+static int ctl_init(gsyeig_ctx *ctx, PCtl *c, int64_t rows)
+{
+    HIP_TRY(hipMemsetAsync(c, 0, PCTL_STAGE_OFFSET, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctl_stage(c), 0xFF, sizeof(double) * (size_t)rows, ctx->stream));
+    return 0;
+}
+
+int ctl_reserve(gsyeig_ctx *ctx, int64_t rows)
+{
+    if (rows <= ctx->ctl_rows) return 0;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->ctl_n) HIP_TRY(hipFree(ctx->ctl_n));
+    if (ctx->ctl_t) HIP_TRY(hipFree(ctx->ctl_t));
+    ctx->ctl_n = ctx->ctl_t = nullptr;
+    ctx->ctl_rows = 0;
+    const int64_t cap = std::max<int64_t>(cdiv(rows, NB) * NB, 65536);
+    HIP_TRY(hipMalloc((void **)&ctx->ctl_n, ctl_bytes(cap)));
+    HIP_TRY(hipMalloc((void **)&ctx->ctl_t, ctl_bytes(cap)));
+    int rc;
+    if ((rc = ctl_init(ctx, ctx->ctl_n, cap)) || (rc = ctl_init(ctx, ctx->ctl_t, cap))) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->ctl_rows = cap;
+    return 0;
+}
+
+// Reads and clears the persistent kernels' sticky wait-expiry flags.
+static int ctl_check(gsyeig_ctx *ctx)
+{
+    unsigned *h = (unsigned *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, &ctx->ctl_n->err, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(h + 1, &ctx->ctl_t->err, sizeof(unsigned), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (h[0] || h[1]) {
+        // a wait expired: restart both control blocks from a clean state
+        int rc;
+        if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)))
+            return rc;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return GSYEIG_ESPIN;
+    }
+    return 0;
+}
+
+#define TRY(expr)                \
+    do {                         \
+        int _rc = (expr);        \
+        if (_rc) return _rc;     \
+    } while (0)
+
+static void opts_fill_defaults(gsyeig_opts *o)
+{
+    memset(o, 0, sizeof(*o));
+    o->prec = GSYEIG_FP64;
+    o->block = 1;
+    o->which = 0;
+    o->invert = 0;
+    o->tol = 1e-12;
+    o->max_steps = 0;  // 0 = min(n, 100 s + 2000)
+    o->check_every = 25;
+    o->seed = 6374;
+    o->v0 = nullptr;
+    o->profile_every = 0;
+}
+
+static int64_t eff_max_steps(int64_t n, int64_t s, const gsyeig_opts *o)
+{
+    int64_t m = (o && o->max_steps > 0) ? o->max_steps : std::min<int64_t>(n, 100 * s + 2000);
+    m = std::min<int64_t>(m, n);
+    return std::max<int64_t>(m, std::min<int64_t>(s, n));
+}
+
+static int64_t round_ld(int64_t n) { return cdiv(n, 64) * 64; }
+
+// ------------------------------------------------------------------ steps
+static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, sizeof(double) * (size_t)cdiv(n, NB) * NB * NB, &p));
+    *Dinv = (double *)p;
+    return launch_diag_inv(U, ldu, n, *Dinv, ctx->stream);
+}
+
+// Sampled kernel timing: events recorded around KI1/KI2/KI3 on the stream;
+// harvested (elapsed times summed) at the next synchronisation point.
+static int prof_harvest(gsyeig_ctx *ctx)
+{
+    for (int i = 0; i + 3 < ctx->npev; i += 4) {
+        float t[3];
+        for (int k = 0; k < 3; ++k) HIP_TRY(hipEventElapsedTime(&t[k], ctx->pev[i + k], ctx->pev[i + k + 1]));
+        for (int k = 0; k < 3; ++k) ctx->prof_ms[k] += t[k];
+        ctx->prof_samples += 1;
+    }
+    ctx->npev = 0;
+    return 0;
+}
+
+// KI1-KI3 into z (z may alias w); tmp is an n-vector of scratch.
+static int apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
+                    int64_t ldu, const double *Dinv, const double *w, double *z, double *tmp,
+                    bool sample = false)
+{
+    sample = sample && ctx->npev + 4 <= 64;
+    hipEvent_t *e = ctx->pev + ctx->npev;
+    if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
+    TRY(launch_trsv_n(U, ldu, n, Dinv, w, tmp, ctx->ctl_n, ctx->stream));
+    if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
+    TRY(launch_symv(ctx, n, A, lda, tmp, z));
+    if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
+    TRY(launch_trsv_t(U, ldu, n, Dinv, z, z, ctx->ctl_t, ctx->stream));
+    if (sample) {
+        HIP_TRY(hipEventRecord(e[3], ctx->stream));
+        ctx->npev += 4;
+    }
+    return 0;
+}
+
+struct LzBufs {
+    double *z, *tmp, *red, *red2, *h, *normpart;
+};
+
+static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_TMP1, sizeof(double) * (size_t)n, &p));
+    b->z = (double *)p;
+    TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
+    b->tmp = (double *)p;
+    const size_t red = (size_t)lz_red_parts(n) * (size_t)(kmax + 8) + (size_t)lz_norm_parts(n) + 1024;
+    TRY(ws_get(ctx, WS_RED, sizeof(double) * red, &p));
+    b->red = (double *)p;
+    b->normpart = b->red + 1024;
+    b->red2 = b->normpart + lz_norm_parts(n);
+    TRY(ws_get(ctx, WS_RED2, sizeof(double) * (size_t)(kmax + 8), &p));
+    b->h = (double *)p;
+    return 0;
+}
+
+// One Lanczos step k (KI1-KI4): w_k = V[:, k] -> w_{k+1} = V[:, k+1].
+static int lz_step(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
+                   int64_t ldu, const double *Dinv, double *V, int64_t ldv, double *alpha,
+                   double *beta, int64_t k, const LzBufs &b, bool sample = false)
+{
+    const double *wk = V + k * ldv;
+    const double *wp = (k > 0) ? V + (k - 1) * ldv : wk;
+    TRY(apply_op(ctx, n, A, lda, U, ldu, Dinv, wk, b.z, b.tmp, sample));
+    TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream));
+    TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream));
+    TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream));
+    TRY(launch_lz_normalize(b.z, V + (k + 1) * ldv, beta, k, n, b.normpart, ctx->stream));
+    return 0;
+}
+
+// KI1-KI5 with convergence checks; Ritz values -> theta (s), vectors -> Y.
+struct LzResult {
+    int64_t steps;
+    int64_t nconv;
+    float t_loop_ms, t_ritz_ms;
+};
+
+static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                    const double *U, int64_t ldu, const double *Dinv, const gsyeig_opts *o,
+                    double *theta_out, double *Y, int64_t ldy, LzResult *res)
+{
+    const int64_t mmax = eff_max_steps(n, s, o);
+    const int64_t ldv = round_ld(n);
+    void *p;
+    TRY(ws_get(ctx, WS_V, sizeof(double) * (size_t)ldv * (size_t)(mmax + 1), &p));
+    double *V = (double *)p;
+    // T: alpha (mmax), beta (mmax), theta (s+1), lastcomp (s)
+    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * s + 16), &p));
+    double *alpha = (double *)p, *beta = alpha + mmax, *theta = beta + mmax, *lastc = theta + s + 1;
+    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)s * 6 * (size_t)mmax, &p));
+    double *tri = (double *)p;
+    LzBufs b;
+    TRY(lz_bufs(ctx, n, mmax, &b));
+    TRY(ctl_reserve(ctx, n));
+    int *nconv_d = (int *)ctx->dscal;
+    int *nconv_h = (int *)ctx->host_pinned;
+
+    HIP_TRY(hipEventRecord(ctx->ev[6], ctx->stream));
+    // w_0
+    if (o->v0) {
+        TRY(launch_normalize_into(o->v0, V, n, b.red, nullptr, ctx->stream));
+    } else {
+        TRY(launch_fill_splitmix(b.z, n, o->seed, ctx->stream));
+        TRY(launch_normalize_into(b.z, V, n, b.red, nullptr, ctx->stream));
+    }
+    const int64_t every = std::max<int64_t>(1, o->check_every);
+    int64_t m = 0, nconv = 0;
+    bool checked_at_m = false;
+    ctx->npev = 0;
+    ctx->prof_samples = 0;
+    ctx->prof_ms[0] = ctx->prof_ms[1] = ctx->prof_ms[2] = 0.0;
+    const int64_t pe = o->profile_every;
+    for (int64_t k = 0; k < mmax; ++k) {
+        const bool sample = pe > 0 && (k % pe) == pe - 1;
+        TRY(lz_step(ctx, n, A, lda, U, ldu, Dinv, V, ldv, alpha, beta, k, b, sample));
+        m = k + 1;
+        checked_at_m = false;
+        if (m >= s && (m % every == 0 || m == mmax)) {
+            TRY(launch_tri_bisect(alpha, beta, m, s, o->which, theta, ctx->stream));
+            TRY(launch_tri_vectors(alpha, beta, m, s, theta, nullptr, 0, tri, 0, lastc, ctx->stream));
+            TRY(launch_conv_count(theta, lastc, beta + (m - 1), s, o->tol, nconv_d, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(nconv_h, nconv_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            TRY(prof_harvest(ctx));
+            nconv = *nconv_h;
+            checked_at_m = true;
+            if (nconv >= s) break;
+        }
+    }
+    if (!checked_at_m) {
+        TRY(launch_tri_bisect(alpha, beta, m, s, o->which, theta, ctx->stream));
+    }
+    HIP_TRY(hipEventRecord(ctx->ev[7], ctx->stream));
+    // Ritz vectors: S (m x s) by inverse iteration, Y = V_m S
+    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)s, &p));
+    double *S = (double *)p;
+    TRY(launch_tri_vectors(alpha, beta, m, s, theta, S, m, tri, 1, lastc, ctx->stream));
+    GemmDesc d{};
+    d.m = n; d.n = s; d.k = m;
+    d.A = V; d.lda = ldv; d.a_layout = 0;
+    d.B = S; d.ldb = m; d.b_layout = 0;
+    d.C = Y; d.ldc = ldy; d.c_layout = 0;
+    d.alpha = 1.0; d.beta = 0.0;
+    TRY(launch_gemm_f64(d, ctx->stream));
+    TRY(launch_copy(theta, theta_out, s, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(prof_harvest(ctx));
+    HIP_TRY(hipEventElapsedTime(&res->t_loop_ms, ctx->ev[6], ctx->ev[7]));
+    HIP_TRY(hipEventElapsedTime(&res->t_ritz_ms, ctx->ev[7], ctx->ev[5]));
+    res->steps = m;
+    res->nconv = nconv;
+    TRY(ctl_check(ctx));
+    return 0;
+}
+
+// GS1: B = U^T U in place (upper triangle), Dinv blocks into WS_DINV.
+static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double **Dinv_out,
+                         int *info_d)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, sizeof(double) * (size_t)cdiv(n, NB) * NB * NB, &p));
+    double *Dinv = (double *)p;
+    *Dinv_out = Dinv;
+    HIP_TRY(hipMemsetAsync(info_d, 0, sizeof(int), ctx->stream));
+    const int64_t nblk = cdiv(n, NB);
+    for (int64_t kb = 0; kb < nblk; ++kb) {
+        TRY(launch_potrf_diag(B, ldb, n, kb, Dinv, info_d, ctx->stream));
+        const int64_t r0 = kb * NB;
+        const int64_t r = std::min<int64_t>(NB, n - r0);
+        const int64_t c0 = r0 + r;
+        const int64_t m2 = n - c0;
+        if (m2 <= 0) break;
+        // panel: U_{k, >k} = U_kk^-T B_{k, >k}   (Dinv_kk^T times the row panel)
+        GemmDesc pd{};
+        pd.m = r; pd.n = m2; pd.k = r;
+        pd.A = Dinv + kb * NB * NB; pd.lda = NB; pd.a_layout = 0;   // A(i,k) = Dinv[k][i]
+        pd.B = B + r0 * ldb + c0; pd.ldb = ldb; pd.b_layout = 1;
+        pd.C = B + r0 * ldb + c0; pd.ldc = ldb; pd.c_layout = 1;
+        pd.alpha = 1.0; pd.beta = 0.0;
+        TRY(launch_gemm_f64(pd, ctx->stream));
+        // trailing update of the upper triangle: B_>k,>k -= P^T P
+        GemmDesc sd{};
+        sd.m = m2; sd.n = m2; sd.k = r;
+        sd.A = B + r0 * ldb + c0; sd.lda = ldb; sd.a_layout = 0;    // A(i,k) = P[k][i]
+        sd.B = B + r0 * ldb + c0; sd.ldb = ldb; sd.b_layout = 1;    // B(k,j) = P[k][j]
+        sd.C = B + c0 * ldb + c0; sd.ldc = ldb; sd.c_layout = 1;
+        sd.alpha = -1.0; sd.beta = 1.0;
+        sd.upper_only = 1;
+        TRY(launch_gemm_f64(sd, ctx->stream));
+    }
+    return 0;
+}
+
+static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                         const double *B, int64_t ldb, const double *Bdiag, const double *Lambda,
+                         const double *X, int64_t ldx, double *res_d)
+{
+    const int64_t ldr = round_ld(n);
+    void *p;
+    TRY(ws_get(ctx, WS_Y, sizeof(double) * (size_t)ldr * (size_t)s, &p));
+    double *AX = (double *)p;
+    TRY(ws_get(ctx, WS_Y2, sizeof(double) * (size_t)ldr * (size_t)s, &p));
+    double *BX = (double *)p;
+    const int PA = fro_parts(n);
+    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)(s * s + 2 * s + 2 * PA + 64), &p));
+    double *G = (double *)p, *cols = G + s * s, *partA = cols + 2 * s, *partB = partA + PA;
+    GemmDesc d{};
+    d.m = n; d.n = s; d.k = n;
+    d.A = A; d.lda = lda; d.a_layout = 1;
+    d.B = X; d.ldb = ldx; d.b_layout = 0;
+    d.C = AX; d.ldc = ldr; d.c_layout = 0;
+    d.alpha = 1.0; d.beta = 0.0;
+    TRY(launch_gemm_f64(d, ctx->stream));
+    d.A = B; d.lda = ldb; d.a_layout = Bdiag ? 2 : 1; d.a_diag = Bdiag;
+    d.C = BX;
+    TRY(launch_gemm_f64(d, ctx->stream));
+    GemmDesc g{};
+    g.m = s; g.n = s; g.k = n;
+    g.A = X; g.lda = ldx; g.a_layout = 1;   // A(i,k) = X^T(i,k) = X[i*ldx + k]
+    g.B = BX; g.ldb = ldr; g.b_layout = 0;
+    g.C = G; g.ldc = s; g.c_layout = 0;
+    g.alpha = 1.0; g.beta = 0.0;
+    TRY(launch_gemm_f64(g, ctx->stream));
+    TRY(launch_check_cols(AX, BX, ldr, X, ldx, n, s, Lambda, cols, ctx->stream));
+    TRY(launch_fro_norm_parts(A, lda, n, 0, nullptr, partA, ctx->stream));
+    TRY(launch_fro_norm_parts(B, ldb, n, Bdiag ? 2 : 0, Bdiag, partB, ctx->stream));
+    TRY(launch_check_finalize(cols, s, G, s, partA, PA, partB, PA, Lambda, res_d, ctx->stream));
+    return 0;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char *gsyeig_version(void) { return "gsyeig-gfx950 0.1.0"; }
+
+int gsyeig_opts_default(gsyeig_opts *opts)
+{
+    if (!opts) return -1;
+    opts_fill_defaults(opts);
+    return 0;
+}
+
+int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
+{
+    if (!ctx_out) return -1;
+    gsyeig_ctx *ctx = new (std::nothrow) gsyeig_ctx;
+    if (!ctx) return GSYEIG_ENOMEM;
+    memset(ctx, 0, sizeof(*ctx));
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->symv_map_n = -1;
+    if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
+    if (hipHostMalloc(&ctx->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return GSYEIG_EHIP;
+    }
+    if (hipMalloc(&ctx->dscal, 4096) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
+    for (int i = 0; i < 8; ++i)
+        if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
+    for (int i = 0; i < 64; ++i)
+        if (hipEventCreate(&ctx->pev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
+    int rc = ctl_reserve(ctx, 65536);
+    if (rc) { delete ctx; return rc; }
+    *ctx_out = ctx;
+    return 0;
+}
+
+int gsyeig_destroy(gsyeig_ctx *ctx)
+{
+    if (!ctx) return -1;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < WS_COUNT; ++i)
+        if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+    if (ctx->ctl_n) (void)hipFree(ctx->ctl_n);
+    if (ctx->ctl_t) (void)hipFree(ctx->ctl_t);
+    if (ctx->dscal) (void)hipFree(ctx->dscal);
+    if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    for (int i = 0; i < 8; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < 64; ++i)
+        if (ctx->pev[i]) (void)hipEventDestroy(ctx->pev[i]);
+    delete ctx;
+    return 0;
+}
+
+int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes)
+{
+    if (n < 1) return -1;
+    if (s < 1 || s > n) return -2;
+    if (!bytes) return -4;
+    gsyeig_opts o;
+    if (opts) o = *opts; else opts_fill_defaults(&o);
+    const int64_t mmax = eff_max_steps(n, s, &o);
+    const int64_t ldv = round_ld(n), nblk = cdiv(n, NB);
+    size_t b = 0;
+    b += sizeof(double) * (size_t)nblk * NB * NB;                 // Dinv
+    b += sizeof(double) * (size_t)ldv * (size_t)(mmax + 1);       // V
+    b += sizeof(double) * (size_t)(2 * mmax + 2 * s + 16);        // T
+    b += sizeof(double) * (size_t)s * 6 * (size_t)mmax;           // tridiagonal scratch
+    b += sizeof(double) * (size_t)mmax * (size_t)s;               // S
+    b += 2 * sizeof(double) * (size_t)ldv * (size_t)s;            // check blocks
+    b += sizeof(double) * (size_t)nblk * nblk * NB;               // SYMV column partials
+    b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
+    b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
+    *bytes = b;
+    return 0;
+}
+
+int gsyeig_potrf(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, const gsyeig_opts *opts,
+                 void *U_lowprec)
+{
+    (void)opts;
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!B) return -3;
+    if (ldb < n) return -4;
+    if (U_lowprec) return -6;
+    double *Dinv;
+    int *info_d = (int *)ctx->dscal + 16;
+    TRY(potrf_enqueue(ctx, n, B, ldb, &Dinv, info_d));
+    int *h = (int *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return h[0];
+}
+
+int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int trans,
+                const double *b, double *x)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!U) return -3;
+    if (ldu < n) return -4;
+    if (trans != 0 && trans != 1) return -5;
+    if (!b) return -6;
+    if (!x) return -7;
+    TRY(ctl_reserve(ctx, n));
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    if (trans == 0) return launch_trsv_n(U, ldu, n, Dinv, b, x, ctx->ctl_n, ctx->stream);
+    return launch_trsv_t(U, ldu, n, Dinv, b, x, ctx->ctl_t, ctx->stream);
+}
+
+int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!x) return -5;
+    if (!y) return -6;
+    return launch_symv(ctx, n, A, lda, x, y);
+}
+
+int gsyeig_apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
+                    int64_t ldu, const double *w, double *z)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!U) return -5;
+    if (ldu < n) return -6;
+    if (!w) return -7;
+    if (!z) return -8;
+    TRY(ctl_reserve(ctx, n));
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    void *p;
+    TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
+    return apply_op(ctx, n, A, lda, U, ldu, Dinv, w, z, (double *)p);
+}
+
+int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, int64_t lda,
+                       const double *U, int64_t ldu, const double *v0, double *alpha, double *beta,
+                       double *V, int64_t ldv)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (k < 1 || k > n) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!U) return -6;
+    if (ldu < n) return -7;
+    if (!v0) return -8;
+    if (!alpha) return -9;
+    if (!beta) return -10;
+    if (!V) return -11;
+    if (ldv < n) return -12;
+    TRY(ctl_reserve(ctx, n));
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    LzBufs b;
+    TRY(lz_bufs(ctx, n, k, &b));
+    TRY(launch_normalize_into(v0, V, n, b.red, nullptr, ctx->stream));
+    for (int64_t j = 0; j < k; ++j) TRY(lz_step(ctx, n, A, lda, U, ldu, Dinv, V, ldv, alpha, beta, j, b));
+    return 0;
+}
+
+int gsyeig_tridiag_eig(gsyeig_ctx *ctx, int64_t m, const double *alpha, const double *beta,
+                       int64_t nwant, int which, double *theta, double *S, int64_t lds)
+{
+    if (!ctx) return -1;
+    if (m < 1) return -2;
+    if (!alpha) return -3;
+    if (!beta && m > 1) return -4;
+    if (nwant < 1 || nwant > m) return -5;
+    if (which != 0 && which != 1) return -6;
+    if (!theta) return -7;
+    if (S && lds < m) return -9;
+    void *p;
+    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * nwant + 16), &p));
+    double *th = (double *)p, *lastc = th + nwant + 1;
+    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)nwant * 6 * (size_t)m, &p));
+    double *tri = (double *)p;
+    TRY(launch_tri_bisect(alpha, beta ? beta : alpha, m, nwant, which, th, ctx->stream));
+    if (S) TRY(launch_tri_vectors(alpha, beta ? beta : alpha, m, nwant, th, S, lds, tri, 1, lastc,
+                                  ctx->stream));
+    return launch_copy(th, theta, nwant, ctx->stream);
+}
+
+int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                   const double *U, int64_t ldu, const gsyeig_opts *opts, double *theta, double *Y,
+                   int64_t ldy, int64_t *steps_out)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (s < 1 || s > n) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!U) return -6;
+    if (ldu < n) return -7;
+    if (!theta) return -9;
+    if (!Y) return -10;
+    if (ldy < n) return -11;
+    gsyeig_opts o;
+    if (opts) o = *opts; else opts_fill_defaults(&o);
+    if (o.prec != GSYEIG_FP64 || o.block != 1 || o.invert) return -8;
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    LzResult r{};
+    TRY(lz_solve(ctx, n, s, A, lda, U, ldu, Dinv, &o, theta, Y, ldy, &r));
+    if (steps_out) *steps_out = r.steps;
+    return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+}
+
+int gsyeig_backsolve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *U, int64_t ldu,
+                     double *Y_to_X, int64_t ldy)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (s < 1) return -3;
+    if (!U) return -4;
+    if (ldu < n) return -5;
+    if (!Y_to_X) return -6;
+    if (ldy < n) return -7;
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    return launch_backsolve(U, ldu, n, s, Dinv, Y_to_X, ldy, ctx->stream);
+}
+
+int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, const double *Bdiag, const double *Lambda,
+                 const double *X, int64_t ldx, gsyeig_info *out)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (s < 1 || s > n) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!B) return -6;
+    if (ldb < n) return -7;
+    if (!Lambda) return -9;
+    if (!X) return -10;
+    if (ldx < n) return -11;
+    if (!out) return -12;
+    double *res_d = (double *)ctx->dscal + 64;
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, Bdiag, Lambda, X, ldx, res_d));
+    double *h = (double *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    out->eta_max = h[0];
+    out->rho_f = h[1];
+    out->omega = h[2];
+    out->normA_f = h[3];
+    out->normB_f = h[4];
+    return 0;
+}
+
+int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
+                 int64_t ldb, const gsyeig_opts *opts, double *Lambda, double *X, int64_t ldx,
+                 gsyeig_info *info)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (s < 1 || s > n) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!B) return -6;
+    if (ldb < n) return -7;
+    gsyeig_opts o;
+    if (opts) o = *opts; else opts_fill_defaults(&o);
+    if (o.prec != GSYEIG_FP64 || o.block != 1 || o.invert || (o.which != 0 && o.which != 1))
+        return -8;
+    if (!Lambda) return -9;
+    if (!X) return -10;
+    if (ldx < n) return -11;
+
+    gsyeig_info inf;
+    memset(&inf, 0, sizeof(inf));
+    void *p;
+    TRY(ws_get(ctx, WS_BDIAG, sizeof(double) * (size_t)n, &p));
+    double *bdiag = (double *)p;
+    int *info_d = (int *)ctx->dscal + 16;
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    TRY(launch_copy_diag(B, ldb, n, bdiag, ctx->stream));
+    double *Dinv;
+    TRY(potrf_enqueue(ctx, n, B, ldb, &Dinv, info_d));
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+    int *hi = (int *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(hi, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (hi[0] != 0) return hi[0];
+
+    LzResult r{};
+    TRY(lz_solve(ctx, n, s, A, lda, B, ldb, Dinv, &o, Lambda, X, ldx, &r));
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
+    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
+    double *res_d = (double *)ctx->dscal + 64;
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, bdiag, Lambda, X, ldx, res_d));
+    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
+    double *h = (double *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    inf.eta_max = h[0];
+    inf.rho_f = h[1];
+    inf.omega = h[2];
+    inf.normA_f = h[3];
+    inf.normB_f = h[4];
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
+    inf.t_ki_ms = r.t_loop_ms;
+    inf.t_ki5_ms = r.t_ritz_ms;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_check_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[4])); inf.t_total_ms = t;
+    inf.steps = r.steps;
+    inf.converged = r.nconv;
+    inf.prof_samples = ctx->prof_samples;
+    inf.t_ki1_ms_sum = ctx->prof_ms[0];
+    inf.t_ki2_ms_sum = ctx->prof_ms[1];
+    inf.t_ki3_ms_sum = ctx->prof_ms[2];
+    if (info) *info = inf;
+    return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+}
+
+}  // extern "C"

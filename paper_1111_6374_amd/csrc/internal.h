@@ -1,0 +1,150 @@
+// internal.h -- shared declarations of the gfx950 solver library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/gsyeig.h"
+
+// Block size of the triangular factor: diagonal blocks of U are NB x NB.
+// One 64-row tile is one wavefront-width of rows and 32 KiB of FP64.
+#define NB 64
+
+// Upper bound on polls in a persistent kernel's wait on another workgroup.
+// A wait that exceeds it records GSYEIG_ESPIN and the workgroup carries on,
+// so a logic error can never hang the GPU.
+#define SPIN_LIMIT (1u << 22)
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Control block of one persistent (chained) kernel launch: counters, then a
+// staging vector (at byte offset PCTL_STAGE_OFFSET) through which solved
+// values are published.  Between launches every staging entry holds
+// STAGE_SENTINEL (an all-ones NaN, never produced by arithmetic); the last
+// workgroup to finish restores it and resets the counters, so the block is
+// ready for the next launch without any host-side memset.
+struct PCtl {
+    unsigned ticket;
+    unsigned done;
+    unsigned err;
+    unsigned pad;
+};
+#define PCTL_STAGE_OFFSET 256
+#define STAGE_SENTINEL 0xFFFFFFFFFFFFFFFFull
+
+__host__ __device__ inline double *ctl_stage(PCtl *c)
+{
+    return reinterpret_cast<double *>(reinterpret_cast<char *>(c) + PCTL_STAGE_OFFSET);
+}
+
+enum WsSlot {
+    WS_DINV = 0,   // n x NB FP64: inverses of the diagonal blocks of U
+    WS_TMP1,       // n FP64
+    WS_TMP2,       // n FP64
+    WS_SYMV_PR,    // SYMV row partials
+    WS_SYMV_PC,    // SYMV column partials
+    WS_RED,        // partial sums of the Lanczos reductions
+    WS_RED2,
+    WS_V,          // Lanczos basis, ldv x (max_steps + 1)
+    WS_T,          // alpha, beta, theta, last components, scalars
+    WS_TRI,        // tridiagonal eigensolver scratch
+    WS_S,          // Ritz coefficient matrix S (m x s)
+    WS_Y,          // n x s blocks (Ritz vectors / check temporaries)
+    WS_Y2,
+    WS_BDIAG,      // saved diagonal of B
+    WS_SYMVMAP,    // SYMV work list
+    WS_COUNT
+};
+
+struct gsyeig_ctx {
+    hipStream_t stream;
+    int device;
+    void *ws[WS_COUNT];
+    size_t ws_bytes[WS_COUNT];
+    PCtl *ctl_n;        // persistent-kernel control blocks (+flags)
+    PCtl *ctl_t;
+    int64_t ctl_rows;   // staging capacity (rows) of each control block
+    int64_t symv_map_n; // n for which WS_SYMVMAP is valid
+    int64_t symv_items;
+    void *host_pinned;  // small pinned host staging area
+    void *dscal;        // small device scratch (info codes, counters, check results)
+    hipEvent_t ev[8];
+    hipEvent_t pev[64];   // sampled per-kernel timing (4 per sampled step)
+    int npev;             // events recorded since the last harvest
+    int64_t prof_samples;
+    double prof_ms[3];
+};
+
+// ---------------------------------------------------------------- helpers
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return GSYEIG_EHIP;       \
+    } while (0)
+
+int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out);
+int ctl_reserve(gsyeig_ctx *ctx, int64_t rows);
+
+// ---------------------------------------------------------------- launchers
+// Each returns 0 or GSYEIG_EHIP; all are asynchronous on `st`.
+// Dense FP64 tiles (MFMA): C = alpha * op(A) op(B) + beta * C.
+// Layout codes: 0 = column-major, 1 = row-major, 2 = symmetric taken from the
+// strict LOWER triangle of a row-major matrix with diagonal from `diag`.
+struct GemmDesc {
+    int64_t m, n, k;
+    const double *A; int64_t lda; int a_layout;
+    const double *B; int64_t ldb; int b_layout;
+    double *C; int64_t ldc; int c_layout;
+    double alpha, beta;
+    const double *a_diag;  // for a_layout == 2
+    int upper_only;        // write only C(i, j) with i <= j (logical indices)
+};
+int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
+
+int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
+int launch_trsv_n(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
+                  double *x, PCtl *ctl, hipStream_t st);
+int launch_trsv_t(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
+                  double *x, PCtl *ctl, hipStream_t st);
+int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x,
+                double *y);
+int launch_potrf_diag(double *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,
+                      hipStream_t st);
+int launch_copy_diag(const double *B, int64_t ldb, int64_t n, double *d, hipStream_t st);
+int launch_backsolve(const double *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv,
+                     double *Y, int64_t ldy, hipStream_t st);
+int launch_sign_normalise(double *X, int64_t ldx, int64_t n, int64_t s, hipStream_t st);
+
+// Lanczos vector kernels (KI4)
+int lz_red_parts(int64_t n);
+int lz_norm_parts(int64_t n);
+int launch_fill_splitmix(double *v, int64_t n, uint64_t seed, hipStream_t st);
+int launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);
+int launch_normalize_into(const double *v, double *w, int64_t n, double *part, double *norm_out,
+                          hipStream_t st);
+int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *alpha,
+                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st);
+int launch_cgs_pass(const double *V, int64_t ldv, int64_t n, int64_t kcols, double *z, double *part,
+                    double *h, double *normpart, hipStream_t st);
+int launch_lz_normalize(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
+                        const double *normpart, hipStream_t st);
+
+// tridiagonal eigensolver (KI5)
+int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_t nwant, int which,
+                      double *theta, hipStream_t st);
+int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64_t nwant,
+                       const double *theta, double *S, int64_t lds, double *scratch, int clustered,
+                       double *lastcomp, hipStream_t st);
+int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
+                      int64_t nwant, double tol, int *nconv, hipStream_t st);
+
+// accuracy check
+int fro_parts(int64_t n);
+int launch_fro_norm_parts(const double *A, int64_t lda, int64_t n, int mode, const double *diag,
+                          double *part, hipStream_t st);
+int launch_check_cols(const double *AX, const double *BX, int64_t ldr, const double *X, int64_t ldx,
+                      int64_t n, int64_t s, const double *lam, double *out, hipStream_t st);
+int launch_check_finalize(const double *cols, int64_t s, const double *G, int64_t ldg,
+                          const double *partA, int PA, const double *partB, int PB,
+                          const double *lam, double *res, hipStream_t st);

@@ -1,0 +1,298 @@
+// k_lanczos.hip -- the Lanczos update z_{k+1} -> w_{k+1} (key KI4 of
+// variant KI, Section 2.3 and Table 1), in FP64:
+//
+//   z := z - beta_{k-1} w_{k-1};  alpha_k := w_k^T z;  z := z - alpha_k w_k
+//   twice:  h := V_k^T z;  z := z - V_k h      (classical Gram-Schmidt, the
+//                                               "orthogonalise twice" rule)
+//   beta_k := ||z||;  w_{k+1} := z / beta_k
+//
+// The basis V (n x (m+1), column-major, each Lanczos vector contiguous) is
+// the dominant traffic: the two Gram-Schmidt passes read it four times per
+// step.  Every reduction is two-stage with a fixed summation order, so the
+// recurrence is bitwise reproducible.
+#include "internal.h"
+
+namespace {
+
+constexpr int RB = 2048;  // rows per partial sum of a vector reduction (256 threads x 8)
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += __shfl_xor(v, 32);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+// Sum over a 256-thread block; the result is returned to every thread.
+__device__ double block_sum(double v, double *sbuf /* >= 4 */)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sbuf[w] = v;
+    __syncthreads();
+    return ((sbuf[0] + sbuf[1]) + (sbuf[2] + sbuf[3]));
+}
+
+// Sum of part[0..P-1] in a fixed tree order, returned to every thread.
+__device__ double sum_parts(const double *part, int P, double *sbuf)
+{
+    double v = 0.0;
+    for (int p = threadIdx.x; p < P; p += 256) v += part[p];
+    return block_sum(v, sbuf);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_fill_splitmix(double *v, int64_t n, uint64_t seed)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = 2.0 * ((double)(splitmix64(seed, (uint64_t)i) >> 11) * 0x1p-53) - 1.0;
+}
+
+__global__ void k_copy(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// part[p] = sum over rows of chunk p of a[i] * b[i]
+__global__ __launch_bounds__(256) void k_dot_parts(const double *a, const double *b, int64_t n,
+                                                   double *part)
+{
+    __shared__ double sbuf[4];
+    const int64_t base = (int64_t)blockIdx.x * RB;
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0; p < RB / 256; ++p) {
+        const int64_t i = base + threadIdx.x + 256 * p;
+        if (i < n) v = fma(a[i], b[i], v);
+    }
+    v = block_sum(v, sbuf);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// w := v / sqrt(sum(part)); optionally records the norm.
+__global__ __launch_bounds__(256) void k_scale_by_norm(const double *v, double *w, int64_t n,
+                                                       const double *part, int P, double *norm_out)
+{
+    __shared__ double sbuf[4];
+    const double nrm = sqrt(sum_parts(part, P, sbuf));
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) w[i] = v[i] / nrm;
+    if (norm_out && blockIdx.x == 0 && threadIdx.x == 0) *norm_out = nrm;
+}
+
+// z := z - beta_{k-1} w_{k-1} (k > 0); part = w_k . z
+__global__ __launch_bounds__(256) void k_lz_three_term(double *z, const double *wprev,
+                                                       const double *wk, const double *beta,
+                                                       int64_t k, int64_t n, double *part)
+{
+    __shared__ double sbuf[4];
+    const double bp = (k > 0) ? beta[k - 1] : 0.0;
+    const int64_t base = (int64_t)blockIdx.x * RB;
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0; p < RB / 256; ++p) {
+        const int64_t i = base + threadIdx.x + 256 * p;
+        if (i < n) {
+            double zi = z[i];
+            if (k > 0) zi = fma(-bp, wprev[i], zi);
+            z[i] = zi;
+            v = fma(wk[i], zi, v);
+        }
+    }
+    v = block_sum(v, sbuf);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// alpha_k = sum(part); z := z - alpha_k w_k
+__global__ __launch_bounds__(256) void k_lz_sub_alpha(double *z, const double *wk, double *alpha,
+                                                      int64_t k, int64_t n, const double *part, int P)
+{
+    __shared__ double sbuf[4];
+    const double a = sum_parts(part, P, sbuf);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) z[i] = fma(-a, wk[i], z[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[k] = a;
+}
+
+// Gram-Schmidt projection, stage 1: part[rc * kcols + c] = V(rows of rc, c)^T z(rows of rc)
+// for the 8 columns of this workgroup's group.
+__global__ __launch_bounds__(256) void k_gemv_t_parts(const double *__restrict__ V, int64_t ldv,
+                                                      int64_t n, int64_t kcols,
+                                                      const double *__restrict__ z,
+                                                      double *__restrict__ part)
+{
+    __shared__ double sred[4][8];
+    const int64_t c0 = (int64_t)blockIdx.x * 8;
+    const int rc = blockIdx.y;
+    const int64_t base = (int64_t)rc * RB;
+    double zr[RB / 256];
+#pragma unroll
+    for (int p = 0; p < RB / 256; ++p) {
+        const int64_t i = base + threadIdx.x + 256 * p;
+        zr[p] = (i < n) ? z[i] : 0.0;
+    }
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        acc[c] = 0.0;
+        if (c0 + c < kcols) {
+            const double *v = V + (c0 + c) * ldv;
+#pragma unroll
+            for (int p = 0; p < RB / 256; ++p) {
+                const int64_t i = base + threadIdx.x + 256 * p;
+                if (i < n) acc[c] = fma(v[i], zr[p], acc[c]);
+            }
+        }
+    }
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double s = wave_sum(acc[c]);
+        if ((threadIdx.x & 63) == 0) sred[w][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && c0 + threadIdx.x < kcols)
+        part[(int64_t)rc * kcols + c0 + threadIdx.x] =
+            (sred[0][threadIdx.x] + sred[1][threadIdx.x]) + (sred[2][threadIdx.x] + sred[3][threadIdx.x]);
+}
+
+// stage 2: h[c] = sum over row chunks
+__global__ void k_gemv_t_reduce(const double *part, int RC, int64_t kcols, double *h)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= kcols) return;
+    double s = 0.0;
+    for (int r = 0; r < RC; ++r) s += part[(int64_t)r * kcols + c];
+    h[c] = s;
+}
+
+// z := z - V h over 64 rows per workgroup (8 waves split the columns);
+// optionally normpart[block] = sum of the updated z^2 over those rows.
+__global__ __launch_bounds__(512) void k_gemv_n_update(const double *__restrict__ V, int64_t ldv,
+                                                       int64_t n, int64_t kcols,
+                                                       const double *__restrict__ h,
+                                                       double *__restrict__ z,
+                                                       double *__restrict__ normpart)
+{
+    __shared__ double s[8][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = r < n;
+    double acc = 0.0;
+    if (ok) {
+        int64_t c = w;
+        for (; c + 24 < kcols; c += 32) {
+            const double v0 = V[c * ldv + r], v1 = V[(c + 8) * ldv + r];
+            const double v2 = V[(c + 16) * ldv + r], v3 = V[(c + 24) * ldv + r];
+            acc = fma(v0, h[c], acc);
+            acc = fma(v1, h[c + 8], acc);
+            acc = fma(v2, h[c + 16], acc);
+            acc = fma(v3, h[c + 24], acc);
+        }
+        for (; c < kcols; c += 8) acc = fma(V[c * ldv + r], h[c], acc);
+    }
+    s[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+        const double sum = ((s[0][lane] + s[1][lane]) + (s[2][lane] + s[3][lane])) +
+                           ((s[4][lane] + s[5][lane]) + (s[6][lane] + s[7][lane]));
+        double zn = 0.0;
+        if (ok) {
+            zn = z[r] - sum;
+            z[r] = zn;
+        }
+        if (normpart) {
+            const double t = wave_sum(zn * zn);
+            if (lane == 0) normpart[blockIdx.x] = t;
+        }
+    }
+}
+
+// beta_k = sqrt(sum(normpart)); w_{k+1} := z / beta_k
+__global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *wnext, double *beta,
+                                                      int64_t k, int64_t n, const double *normpart,
+                                                      int P)
+{
+    __shared__ double sbuf[4];
+    const double b = sqrt(sum_parts(normpart, P, sbuf));
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) wnext[i] = z[i] / b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
+}
+
+inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
+
+}  // namespace
+
+int lz_red_parts(int64_t n) { return (int)cdiv(n, RB); }
+int lz_norm_parts(int64_t n) { return (int)cdiv(n, 64); }
+
+int launch_fill_splitmix(double *v, int64_t n, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_splitmix, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, v, n, seed);
+    return ok();
+}
+
+int launch_copy(const double *src, double *dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+    return ok();
+}
+
+int launch_normalize_into(const double *v, double *w, int64_t n, double *part, double *norm_out,
+                          hipStream_t st)
+{
+    const int P = lz_red_parts(n);
+    hipLaunchKernelGGL(k_dot_parts, dim3(P), dim3(256), 0, st, v, v, n, part);
+    if (ok()) return GSYEIG_EHIP;
+    hipLaunchKernelGGL(k_scale_by_norm, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, v, w, n,
+                       (const double *)part, P, norm_out);
+    return ok();
+}
+
+int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *alpha,
+                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st)
+{
+    const int P = lz_red_parts(n);
+    hipLaunchKernelGGL(k_lz_three_term, dim3(P), dim3(256), 0, st, z, wprev, wk, beta, k, n, part);
+    if (ok()) return GSYEIG_EHIP;
+    hipLaunchKernelGGL(k_lz_sub_alpha, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wk, alpha,
+                       k, n, (const double *)part, P);
+    return ok();
+}
+
+int launch_cgs_pass(const double *V, int64_t ldv, int64_t n, int64_t kcols, double *z, double *part,
+                    double *h, double *normpart, hipStream_t st)
+{
+    const int RC = lz_red_parts(n);
+    hipLaunchKernelGGL(k_gemv_t_parts, dim3((unsigned)cdiv(kcols, 8), RC), dim3(256), 0, st, V, ldv,
+                       n, kcols, (const double *)z, part);
+    if (ok()) return GSYEIG_EHIP;
+    hipLaunchKernelGGL(k_gemv_t_reduce, dim3((unsigned)cdiv(kcols, 256)), dim3(256), 0, st,
+                       (const double *)part, RC, kcols, h);
+    if (ok()) return GSYEIG_EHIP;
+    hipLaunchKernelGGL(k_gemv_n_update, dim3((unsigned)cdiv(n, 64)), dim3(512), 0, st, V, ldv, n,
+                       kcols, (const double *)h, z, normpart);
+    return ok();
+}
+
+int launch_lz_normalize(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
+                        const double *normpart, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_normalize, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wnext,
+                       beta, k, n, normpart, lz_norm_parts(n));
+    return ok();
+}

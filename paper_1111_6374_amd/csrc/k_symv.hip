@@ -1,0 +1,135 @@
+// k_symv.hip -- y = A x for symmetric A in full storage, key KI2 of
+// variant KI (Table 1), reading only the upper triangle (n(n+1)/2 values).
+//
+// Work items are runs of up to SYMV_CH 64x64 tiles along one block row I of
+// the upper triangle.  Each tile A_IJ (J >= I) is loaded once and used twice:
+//   row part     y_I += A_IJ x_J           (summed over the run)
+//   column part  y_J += A_IJ^T x_I  (J > I; the diagonal tile is applied
+//                                    once, from full storage)
+// Partial results go to a scratch area and a second kernel sums them in a
+// fixed order, so the result is bitwise reproducible run to run.
+#include <vector>
+
+#include "internal.h"
+
+#define SYMV_CH 4
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A, int64_t lda,
+                                                    int64_t n, int nblk, int maxch,
+                                                    const double *__restrict__ x,
+                                                    const int2 *__restrict__ items,
+                                                    double *__restrict__ Pr,
+                                                    double *__restrict__ Pc)
+{
+    __shared__ double s_part[4][NB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int2 it = items[blockIdx.x];
+    const int I = it.x, J0 = it.y;
+    const int J1 = (J0 + SYMV_CH < nblk) ? J0 + SYMV_CH : nblk;
+    const int64_t r0 = (int64_t)I * NB;
+    const int c = 16 * w + (lane & 15);
+    const int rg = lane >> 4;
+    const double *Arow = A + (r0 + rg) * lda;
+
+    double a[SYMV_CH][16], xj[SYMV_CH];
+#pragma unroll
+    for (int t = 0; t < SYMV_CH; ++t) {
+        const int J = J0 + t;
+        const int64_t col = (int64_t)J * NB + c;
+        const bool colok = (J < J1) && (col < n);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const bool ok = colok && (r0 + rg + 4 * q < n);
+            a[t][q] = ok ? Arow[(int64_t)(4 * q) * lda + col] : 0.0;
+        }
+        xj[t] = colok ? x[col] : 0.0;
+    }
+    double xi[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xi[q] = (r0 + rg + 4 * q < n) ? x[r0 + rg + 4 * q] : 0.0;
+
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < SYMV_CH; ++t) {
+        const int J = J0 + t;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = fma(a[t][q], xj[t], acc[q]);
+        if (J < J1 && J > I) {
+            double cs = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) cs = fma(a[t][q], xi[q], cs);
+            cs += __shfl_xor(cs, 16);
+            cs += __shfl_xor(cs, 32);
+            if (rg == 0) Pc[((int64_t)J * nblk + I) * NB + c] = cs;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        double v = acc[q];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        acc[q] = v;
+    }
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s_part[w][rg + 4 * q] = acc[q];
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int ch = (J0 - I) / SYMV_CH;
+        Pr[((int64_t)I * maxch + ch) * NB + tid] =
+            s_part[0][tid] + s_part[1][tid] + s_part[2][tid] + s_part[3][tid];
+    }
+}
+
+// y_K = sum of the row parts of block row K + column parts of tiles (I, K), I < K.
+__global__ __launch_bounds__(64) void k_symv_reduce(const double *__restrict__ Pr,
+                                                    const double *__restrict__ Pc, int nblk,
+                                                    int maxch, int64_t n, double *__restrict__ y)
+{
+    const int K = blockIdx.x, t = threadIdx.x;
+    const int nch = (nblk - K + SYMV_CH - 1) / SYMV_CH;
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += Pr[((int64_t)K * maxch + ch) * NB + t];
+    const double *pc = Pc + (int64_t)K * nblk * NB + t;
+    for (int I = 0; I < K; ++I) s += pc[(int64_t)I * NB];
+    const int64_t row = (int64_t)K * NB + t;
+    if (row < n) y[row] = s;
+}
+
+}  // namespace
+
+int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)
+{
+    const int nblk = (int)cdiv(n, NB);
+    const int maxch = (int)cdiv(nblk, SYMV_CH);
+    int rc;
+    if (ctx->symv_map_n != n) {
+        std::vector<int2> items;
+        for (int I = 0; I < nblk; ++I)
+            for (int J0 = I; J0 < nblk; J0 += SYMV_CH) items.push_back(make_int2(I, J0));
+        void *p;
+        if ((rc = ws_get(ctx, WS_SYMVMAP, items.size() * sizeof(int2), &p))) return rc;
+        HIP_TRY(hipMemcpyAsync(p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->symv_map_n = n;
+        ctx->symv_items = (int64_t)items.size();
+    }
+    void *pr, *pc;
+    if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * maxch * NB, &pr))) return rc;
+    if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &pc))) return rc;
+    hipLaunchKernelGGL(k_symv_tiles, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
+                       lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr,
+                       (double *)pc);
+    if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(64), 0, ctx->stream, (const double *)pr,
+                       (const double *)pc, nblk, maxch, n, y);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}

@@ -1,0 +1,311 @@
+// k_tridiag.hip -- eigenpairs of the Lanczos tridiagonal T_m (key KI5,
+// Section 2.3: the extremal eigenvalues of T_m approximate those of C).
+//
+//  * Eigenvalues: Sturm-sequence bisection.  One wave64 per wanted index;
+//    each round evaluates the inertia count at 64 interior points of the
+//    current interval at once (multisection), shrinking it 65x per round.
+//  * Eigenvectors: inverse iteration with T - theta I factored by Gaussian
+//    elimination with partial pivoting (a third super-diagonal appears on
+//    row swaps).  Eigenvalues closer than 1e-3 ||T|| form a cluster that one
+//    workgroup processes in order, re-orthogonalising each new vector
+//    against the cluster's earlier ones after every solve.
+//  * The recurrences are inherently sequential; a wave runs them uniformly
+//    with the operands of 64 consecutive rows held one per lane and read
+//    with readlane, so the loop never waits on memory.
+#include "internal.h"
+
+namespace {
+
+constexpr double EPS = 0x1p-53;
+
+__device__ __forceinline__ double rdlane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Gershgorin interval and the pivot floor, computed by one wave.
+__device__ void gershgorin(const double *alpha, const double *beta, int64_t m, double *gl,
+                           double *gu, double *pivmin)
+{
+    const int lane = threadIdx.x & 63;
+    double lo = INFINITY, hi = -INFINITY, b2 = 0.0;
+    for (int64_t j = lane; j < m; j += 64) {
+        const double bl = (j > 0) ? fabs(beta[j - 1]) : 0.0;
+        const double br = (j < m - 1) ? fabs(beta[j]) : 0.0;
+        lo = fmin(lo, alpha[j] - bl - br);
+        hi = fmax(hi, alpha[j] + bl + br);
+        if (j < m - 1) b2 = fmax(b2, beta[j] * beta[j]);
+    }
+    *gl = wave_min(lo);
+    *gu = wave_max(hi);
+    *pivmin = 0x1p-1022 * fmax(1.0, wave_max(b2));
+}
+
+// number of eigenvalues of T below sigma (LDL^T pivots of T - sigma I)
+__device__ int sturm_count(const double *alpha, const double *beta, int64_t m, double sigma,
+                           double pivmin)
+{
+    double q = alpha[0] - sigma;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int64_t j = 1; j < m; ++j) {
+        const double b = beta[j - 1];
+        q = (alpha[j] - sigma) - (b * b) / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// theta[i] for i < nwant: the wanted eigenvalues ascending; theta[nwant]: the
+// opposite extreme (used for ||T||).
+__global__ __launch_bounds__(64) void k_tri_bisect(const double *__restrict__ alpha,
+                                                   const double *__restrict__ beta, int64_t m,
+                                                   int64_t nwant, int which, double *theta)
+{
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    int64_t idx;
+    if (i < nwant) idx = (which == 0) ? i : m - nwant + i;
+    else idx = (which == 0) ? m - 1 : 0;
+    double gl, gu, pivmin;
+    gershgorin(alpha, beta, m, &gl, &gu, &pivmin);
+    const double tn = fmax(fabs(gl), fabs(gu));
+    double lo = gl - 4.0 * EPS * tn - 2.0 * pivmin;
+    double hi = gu + 4.0 * EPS * tn + 2.0 * pivmin;
+    for (int round = 0; round < 64; ++round) {
+        if (hi - lo <= 4.0 * EPS * fmax(fabs(lo), fabs(hi)) || hi - lo <= 2.0 * EPS * tn) break;
+        const double sig = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const int cnt = sturm_count(alpha, beta, m, sig, pivmin);
+        const unsigned long long up = __ballot(cnt > idx);
+        if (up == 0ull) {
+            lo = rdlane(sig, 63);
+        } else {
+            const int f = __ffsll((long long)up) - 1;
+            const double nhi = rdlane(sig, f);
+            const double nlo = (f == 0) ? lo : rdlane(sig, f - 1);
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (lane == 0) theta[i] = 0.5 * (lo + hi);
+}
+
+// LU of T - lam I with partial pivoting; factors go to f (5 arrays of m):
+// u0 (diagonal of U), u1, u2 (super-diagonals), mult, piv (0/1).
+__device__ void tri_lu(const double *alpha, const double *beta, int64_t m, double lam,
+                       double pivtiny, double *f)
+{
+    double *u0 = f, *u1 = f + m, *u2 = f + 2 * m, *ml = f + 3 * m, *pv = f + 4 * m;
+    const int lane = threadIdx.x & 63;
+    double a = alpha[0] - lam;
+    double b = (m > 1) ? beta[0] : 0.0;
+    for (int64_t j0 = 0; j0 < m; j0 += 64) {
+        // operands of rows j0..j0+63 and j0+1..j0+64, one per lane
+        const int64_t jl = j0 + lane;
+        const double al1 = (jl + 1 < m) ? alpha[jl + 1] - lam : 0.0;
+        const double be0 = (jl < m - 1) ? beta[jl] : 0.0;
+        const double be1 = (jl + 1 < m - 1) ? beta[jl + 1] : 0.0;
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0, rm = 0.0, rp = 0.0;
+        const int cnt = (m - j0 < 64) ? (int)(m - j0) : 64;
+        for (int t = 0; t < cnt; ++t) {
+            const int64_t j = j0 + t;
+            double o0, o1, o2, om, op;
+            if (j == m - 1) {
+                if (fabs(a) < pivtiny) a = (a < 0.0) ? -pivtiny : pivtiny;
+                o0 = a; o1 = 0.0; o2 = 0.0; om = 0.0; op = 0.0;
+            } else {
+                const double sub = rdlane(be0, t);
+                const double d1 = rdlane(al1, t);
+                const double e1 = rdlane(be1, t);
+                if (fabs(a) >= fabs(sub)) {
+                    if (fabs(a) < pivtiny) a = (a < 0.0) ? -pivtiny : pivtiny;
+                    const double l = sub / a;
+                    o0 = a; o1 = b; o2 = 0.0; om = l; op = 0.0;
+                    a = d1 - l * b;
+                    b = e1;
+                } else {
+                    const double l = a / sub;
+                    o0 = sub; o1 = d1; o2 = e1; om = l; op = 1.0;
+                    a = b - l * d1;
+                    b = -l * e1;
+                }
+            }
+            if (lane == t) { r0 = o0; r1 = o1; r2 = o2; rm = om; rp = op; }
+        }
+        if (jl < m) { u0[jl] = r0; u1[jl] = r1; u2[jl] = r2; ml[jl] = rm; pv[jl] = rp; }
+    }
+}
+
+// x := (T - lam I)^-1 x using the factors (wave 0 only; x in global memory).
+__device__ void tri_solve(const double *f, int64_t m, double *x)
+{
+    const double *u0 = f, *u1 = f + m, *u2 = f + 2 * m, *ml = f + 3 * m, *pv = f + 4 * m;
+    const int lane = threadIdx.x & 63;
+    // forward: y = L^-1 P x
+    double r = x[0];
+    for (int64_t j0 = 0; j0 < m; j0 += 64) {
+        const int64_t jl = j0 + lane;
+        const double mm = (jl < m) ? ml[jl] : 0.0;
+        const double pp = (jl < m) ? pv[jl] : 0.0;
+        const double xn = (jl + 1 < m) ? x[jl + 1] : 0.0;
+        double yout = 0.0;
+        const int cnt = (m - j0 < 64) ? (int)(m - j0) : 64;
+        for (int t = 0; t < cnt; ++t) {
+            const int64_t j = j0 + t;
+            double y;
+            if (j == m - 1) {
+                y = r;
+            } else {
+                const double l = rdlane(mm, t), xj1 = rdlane(xn, t);
+                if (rdlane(pp, t) == 0.0) { y = r; r = xj1 - l * r; }
+                else { y = xj1; r = r - l * xj1; }
+            }
+            if (lane == t) yout = y;
+        }
+        if (jl < m) x[jl] = yout;
+    }
+    // back: U z = y, from the bottom
+    double z1 = 0.0, z2 = 0.0;  // z[j+1], z[j+2]
+    for (int64_t j1 = m; j1 > 0; j1 -= 64) {
+        const int64_t j0 = (j1 - 64 > 0) ? j1 - 64 : 0;
+        const int64_t jl = j0 + lane;
+        const bool in = jl < j1;
+        const double a0 = in ? u0[jl] : 1.0, a1 = in ? u1[jl] : 0.0, a2 = in ? u2[jl] : 0.0;
+        const double yv = in ? x[jl] : 0.0;
+        double zout = 0.0;
+        for (int t = (int)(j1 - j0) - 1; t >= 0; --t) {
+            const double z = (rdlane(yv, t) - rdlane(a1, t) * z1 - rdlane(a2, t) * z2) / rdlane(a0, t);
+            z2 = z1;
+            z1 = z;
+            if (lane == t) zout = z;
+        }
+        if (in) x[jl] = zout;
+    }
+}
+
+__device__ double block_dot(const double *a, const double *b, int64_t m, double *sbuf)
+{
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v = fma(a[i], b[i], v);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sbuf[0] + sbuf[1]) + (sbuf[2] + sbuf[3]);
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One workgroup per wanted eigenvalue; with `clustered`, only the first
+// index of each cluster does work and it computes the whole cluster.
+__global__ __launch_bounds__(256) void k_tri_vectors(const double *__restrict__ alpha,
+                                                     const double *__restrict__ beta, int64_t m,
+                                                     int64_t nwant, const double *__restrict__ theta,
+                                                     double *S, int64_t lds, double *scratch,
+                                                     int clustered, double *lastcomp)
+{
+    __shared__ double sbuf[4];
+    const int64_t i0 = blockIdx.x;
+    const double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
+    const double ortol = 1e-3 * tn;
+    if (clustered && i0 > 0 && theta[i0] - theta[i0 - 1] <= ortol) return;
+    int64_t i1 = i0 + 1;
+    if (clustered)
+        while (i1 < nwant && theta[i1] - theta[i1 - 1] <= ortol) ++i1;
+    double *f = scratch + i0 * 6 * m;
+    double *x = f + 5 * m;
+    const double pivtiny = EPS * fmax(tn, 0x1p-1000);
+    const double pert = 10.0 * EPS * fmax(tn, 0x1p-1000);
+    double lam_prev = -INFINITY;
+    for (int64_t j = i0; j < i1; ++j) {
+        double lam = theta[j];
+        if (j > i0 && lam - lam_prev < pert) lam = lam_prev + pert;  // separate equal Ritz values
+        lam_prev = lam;
+        if (threadIdx.x < 64) tri_lu(alpha, beta, m, lam, pivtiny, f);
+        for (int64_t t = threadIdx.x; t < m; t += blockDim.x)
+            x[t] = 2.0 * ((double)(mix64(0x5DEECE66Dull * (uint64_t)(j + 1) + (uint64_t)t) >> 11) *
+                          0x1p-53) - 1.0;
+        __syncthreads();
+        for (int it = 0; it < 3; ++it) {
+            if (threadIdx.x < 64) tri_solve(f, m, x);
+            __syncthreads();
+            if (clustered && S) {
+                for (int64_t p = i0; p < j; ++p) {
+                    const double *sp = S + p * lds;
+                    const double d = block_dot(sp, x, m, sbuf);
+                    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) x[t] -= d * sp[t];
+                    __syncthreads();
+                }
+            }
+            const double nrm = sqrt(block_dot(x, x, m, sbuf));
+            const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+            for (int64_t t = threadIdx.x; t < m; t += blockDim.x) x[t] *= inv;
+            __syncthreads();
+        }
+        if (S)
+            for (int64_t t = threadIdx.x; t < m; t += blockDim.x) S[j * lds + t] = x[t];
+        if (lastcomp && threadIdx.x == 0) lastcomp[j] = fabs(x[m - 1]);
+        __syncthreads();
+    }
+}
+
+// nconv = #{ i : |beta_m| lastcomp[i] <= tol ||T|| },  ||T|| ~ max |theta|
+__global__ __launch_bounds__(64) void k_conv_count(const double *theta, const double *lastcomp,
+                                                   const double *beta_m, int64_t nwant, double tol,
+                                                   int *nconv)
+{
+    const double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
+    const double bm = fabs(*beta_m);
+    int c = 0;
+    for (int64_t i = threadIdx.x; i < nwant; i += 64) c += (bm * lastcomp[i] <= tol * tn);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (threadIdx.x == 0) *nconv = c;
+}
+
+inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
+
+}  // namespace
+
+int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_t nwant, int which,
+                      double *theta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)(nwant + 1)), dim3(64), 0, st, alpha, beta, m,
+                       nwant, which, theta);
+    return ok();
+}
+
+int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64_t nwant,
+                       const double *theta, double *S, int64_t lds, double *scratch, int clustered,
+                       double *lastcomp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tri_vectors, dim3((unsigned)nwant), dim3(256), 0, st, alpha, beta, m, nwant,
+                       theta, S, lds, scratch, clustered, lastcomp);
+    return ok();
+}
+
+int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
+                      int64_t nwant, double tol, int *nconv, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, tol,
+                       nconv);
+    return ok();
+}

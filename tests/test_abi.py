@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-side argument validation (no GPU call is made on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsyeig.h")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import paper_1111_6374_amd as gs
+
+    if not os.path.exists(gs.LIB_PATH):
+        from paper_1111_6374_amd import build
+
+        build.build()
+    gs.lib()
+    return gs
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(gsyeig_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("gsyeig_potrf", "gsyeig_lanczos", "gsyeig_backsolve", "gsyeig_solve"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(gs):
+    L = gs.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert sorted(gs.EXPORTS) == header_functions()
+
+
+def test_exports_are_extern_c(gs):
+    out = os.popen(f"nm -D --defined-only {gs.LIB_PATH}").read()
+    for name in header_functions():
+        assert re.search(rf"\bT {name}$", out, re.M), name
+
+
+def test_version_and_defaults(gs):
+    assert "gfx950" in gs.gsyeig_version()
+    o = gs.gsyeig_opts_default()
+    assert (o.prec, o.block, o.which, o.invert) == (0, 1, 0, 0)
+    assert o.tol == 1e-12 and o.check_every == 25 and o.seed == 6374 and not o.v0
+    assert ctypes.sizeof(gs.gsyeig_opts) == 64 and o.profile_every == 0
+
+
+def test_workspace_size(gs):
+    rc, b = gs.gsyeig_workspace_size(16384, 100)
+    assert rc == 0
+    # V alone: n x (min(n, 100 s + 2000) + 1) doubles
+    assert b >= 16384 * (12000 + 1) * 8
+    assert gs.gsyeig_workspace_size(0, 1)[0] == -1
+    assert gs.gsyeig_workspace_size(10, 11)[0] == -2
+
+
+def test_null_context_is_rejected_without_gpu(gs):
+    assert gs.gsyeig_solve(None, 10, 2, 1, 10, 1, 10, None, 1, 1, 10)[0] == -1
+    assert gs.gsyeig_potrf(None, 10, 1, 10) == -1
+    assert gs.gsyeig_trsv(None, 10, 1, 10, 0, 1, 1) == -1
+    assert gs.gsyeig_destroy(None) == -1
+    assert gs.lib().gsyeig_opts_default(None) == -1
+
+
+def test_binding_refuses_cpu_tensors(gs):
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        gs._p(torch.zeros(3, dtype=torch.float64))

@@ -1,0 +1,196 @@
+"""End-to-end parity of gsyeig_solve (GS1 -> KI1..KI5 -> BT1 -> check)
+against the CPU oracle and the generators' known answers.
+
+Tolerance (FP64 path): eigenvalues |dl| <= 1e-10 max|l| (the acceptance bar;
+the path reaches ~1e-14), per-pair backward error eta <= 1e-12, and
+B-orthonormality ||I - X^T B X||_F <= 1e-10."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def gs(torch):
+    import paper_1111_6374_amd as gs
+
+    gs.lib()
+    return gs
+
+
+@pytest.fixture(scope="module")
+def solver(gs, torch):
+    s = gs.Solver()
+    yield s
+    s.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def run(torch, solver, A, B, s, **kw):
+    import paper_1111_6374_amd as gs
+
+    o = gs.gsyeig_opts_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    Lam, X, info = solver.solve(dev(torch, A), dev(torch, B), s, o)
+    torch.cuda.synchronize()
+    return Lam.cpu().numpy(), X.cpu().numpy(), info
+
+
+def align(X, Xref):
+    sgn = np.sign(np.sum(X * Xref, axis=1))
+    sgn[sgn == 0] = 1
+    return sgn[:, None] * Xref
+
+
+@pytest.mark.parametrize("n,s", [(512, 10), (333, 7), (130, 13), (64, 5)])
+def test_solve_known_spectrum_vs_oracle(torch, solver, orc, n, s):
+    say("solve-known", n, s)
+    d = gen.known_spectrum(n, seed=6374, stream=(0, n))
+    lam, X, info = run(torch, solver, d["A"], d["B"], s)
+    assert info["rc"] == 0, info
+    lam_o, X_o = orc.gsyeig(d["A"], d["B"], s)
+    lam_true = np.sort(d["lam"])[:s]
+    scale = np.max(np.abs(d["lam"]))
+    assert np.max(np.abs(lam - lam_o)) <= 1e-10 * scale
+    assert np.max(np.abs(lam - lam_true)) <= 1e-10 * scale
+    assert np.max(np.abs(X - align(X, X_o))) <= 1e-8 * np.max(np.abs(X_o))
+    m = orc.metrics(d["A"], d["B"], lam, X, lam_true)
+    assert m["eta_max"] <= 1e-12 and m["omega"] <= 1e-10
+    # the device check agrees with the oracle's metrics
+    assert info["eta_max"] <= 1e-12 and abs(info["eta_max"] - m["eta_max"]) <= 0.5 * m["eta_max"] + 1e-16
+    assert abs(info["omega"] - m["omega"]) <= 1e-12
+    assert info["steps"] >= s and info["converged"] >= s
+
+
+def test_solve_full_spectrum_small_vs_brute_force(torch, solver, orc):
+    n = 40
+    A = gen.random_symmetric(n, seed=201)
+    B = gen.random_spd(n, seed=202)
+    say("solve-bruteforce", n)
+    lam, X, info = run(torch, solver, A, B, n)
+    ref = orc.bisect_eigs(A, B, range(n))
+    assert np.max(np.abs(lam - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert orc.metrics(A, B, lam, X)["eta_max"] <= 1e-12
+
+
+def test_solve_largest(torch, solver, orc):
+    n, s = 300, 6
+    d = gen.known_spectrum(n, seed=203)
+    say("solve-largest", n, s)
+    lam, X, info = run(torch, solver, d["A"], d["B"], s, which=1)
+    assert np.max(np.abs(lam - np.sort(d["lam"])[-s:])) <= 1e-10
+    assert orc.metrics(d["A"], d["B"], lam, X)["eta_max"] <= 1e-12
+
+
+def test_solve_fem_closed_form(torch, solver, orc):
+    n, s = 200, 5
+    K, M = gen.fem_pencil(n)
+    say("solve-fem", n, s)
+    lam, X, info = run(torch, solver, K, M, s)
+    lam_ref, X_ref = gen.fem_eigs(n, s)
+    h = 1.0 / (n + 1)
+    assert np.max(np.abs(lam - lam_ref)) <= 1e-10 * 12.0 / h**2
+    assert np.max(np.abs(X - align(X, X_ref))) <= 1e-6
+    assert orc.metrics(K, M, lam, X)["eta_max"] <= 1e-12
+
+
+def test_solve_special_cases(torch, solver, orc):
+    # n = 1
+    say("solve-n1")
+    lam, X, _ = run(torch, solver, np.array([[3.0]]), np.array([[4.0]]), 1)
+    assert abs(lam[0] - 0.75) <= 1e-15 and abs(X[0, 0] - 0.5) <= 1e-15
+    # diagonal pencil
+    n, s = 90, 4
+    A, B, a, b = gen.diagonal_pencil(n, seed=204)
+    say("solve-diag", n)
+    lam, X, _ = run(torch, solver, A, B, s)
+    r = a / b
+    order = np.argsort(r)[:s]
+    assert np.max(np.abs(lam - r[order])) <= 1e-13
+    Xr = np.zeros((s, n))
+    Xr[np.arange(s), order] = 1 / np.sqrt(b[order])
+    assert np.max(np.abs(X - Xr)) <= 1e-10
+
+
+def test_solve_sign_convention(torch, solver):
+    n, s = 256, 8
+    d = gen.known_spectrum(n, seed=205)
+    say("solve-sign", n)
+    _, X, _ = run(torch, solver, d["A"], d["B"], s)
+    for x in X:
+        p = int(np.argmax(np.abs(x)))
+        assert x[p] > 0
+
+
+def test_solve_errors(torch, solver, gs):
+    n = 100
+    A = gen.random_symmetric(n, seed=206)
+    Bn = gen.random_spd(n, seed=207)
+    Bn[40, 40] = -1.0
+    say("solve-errors", n)
+    Lam = torch.empty(3, dtype=torch.float64, device="cuda")
+    X = torch.empty(3, n, dtype=torch.float64, device="cuda")
+    rc, _ = gs.gsyeig_solve(solver.ctx, n, 3, dev(torch, A), n, dev(torch, Bn), n, None, Lam, X, n)
+    assert 1 <= rc <= 41
+    assert gs.gsyeig_solve(solver.ctx, n, n + 1, dev(torch, A), n, dev(torch, Bn), n, None, Lam, X, n)[0] == -3
+    assert gs.gsyeig_solve(solver.ctx, n, 3, dev(torch, A), n - 1, dev(torch, Bn), n, None, Lam, X, n)[0] == -5
+    assert gs.gsyeig_solve(solver.ctx, n, 3, None, n, dev(torch, Bn), n, None, Lam, X, n)[0] == -4
+
+
+def test_solve_not_converged_flag(torch, solver):
+    n, s = 400, 10
+    d = gen.known_spectrum(n, seed=208)
+    say("solve-noconv", n)
+    lam, X, info = run(torch, solver, d["A"], d["B"], s, max_steps=15, check_every=5)
+    import paper_1111_6374_amd as gs
+
+    assert info["rc"] == gs.GSYEIG_ENOCONV and info["steps"] == 15
+
+
+def test_lanczos_entry_seed_equals_explicit_start(torch, gs, orc):
+    # the library's SplitMix64 start vector is the generator's, bit for bit
+    n, s = 200, 4
+    d = gen.known_spectrum(n, seed=209)
+    U = dev(torch, d["U"])
+    A = dev(torch, d["A"])
+    out = []
+    for use_v0 in (False, True):
+        o = gs.gsyeig_opts_default()
+        o.seed = 99
+        v0 = dev(torch, gen.splitmix64_uniform(n, 99))
+        if use_v0:
+            o.v0 = v0.data_ptr()
+        th = torch.empty(s, dtype=torch.float64, device="cuda")
+        Y = torch.empty(s, n, dtype=torch.float64, device="cuda")
+        with gs.Solver() as sv:
+            say("lanczos-entry", use_v0)
+            rc, steps = gs.gsyeig_lanczos(sv.ctx, n, s, A, n, U, n, o, th, Y, n)
+        assert rc == 0
+        torch.cuda.synchronize()
+        out.append((th.cpu().numpy(), steps))
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.max(np.abs(out[0][0] - np.sort(d["lam"])[:s])) <= 1e-12
