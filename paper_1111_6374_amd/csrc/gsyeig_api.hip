@@ -114,12 +114,18 @@ static int64_t eff_max_steps(int64_t n, int64_t s, const gsyeig_opts *o)
 static int64_t round_ld(int64_t n) { return cdiv(n, 64) * 64; }
 
 // ------------------------------------------------------------------ steps
+// Block data of the factor used by the solves, one WS_DINV allocation:
+// [Dinv_i | M_i = Dinv_i U_{i,i+1} | M'_i = Dinv_i^T U_{i-1,i}^T], 64x64 each.
+static size_t tri_aux_bytes(int64_t n) { return 3 * sizeof(double) * (size_t)cdiv(n, NB) * NB * NB; }
+static const double *aux_m(const double *Dinv, int64_t n) { return Dinv + cdiv(n, NB) * NB * NB; }
+
 static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv)
 {
     void *p;
-    TRY(ws_get(ctx, WS_DINV, sizeof(double) * (size_t)cdiv(n, NB) * NB * NB, &p));
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     *Dinv = (double *)p;
-    return launch_diag_inv(U, ldu, n, *Dinv, ctx->stream);
+    TRY(launch_diag_inv(U, ldu, n, *Dinv, ctx->stream));
+    return launch_make_m(U, ldu, n, *Dinv, *Dinv + cdiv(n, NB) * NB * NB, ctx->stream);
 }
 
 // Sampled kernel timing: events recorded around KI1/KI2/KI3 on the stream;
@@ -144,11 +150,11 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, co
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
-    TRY(launch_trsv_n(U, ldu, n, Dinv, w, tmp, ctx->ctl_n, ctx->stream));
+    TRY(launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), w, tmp, ctx->ctl_n, ctx->stream));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
     TRY(launch_symv(ctx, n, A, lda, tmp, z));
     if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
-    TRY(launch_trsv_t(U, ldu, n, Dinv, z, z, ctx->ctl_t, ctx->stream));
+    TRY(launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), z, z, ctx->ctl_t, ctx->stream));
     if (sample) {
         HIP_TRY(hipEventRecord(e[3], ctx->stream));
         ctx->npev += 4;
@@ -211,7 +217,7 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int6
     // T: alpha (mmax), beta (mmax), theta (s+1), lastcomp (s)
     TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * s + 16), &p));
     double *alpha = (double *)p, *beta = alpha + mmax, *theta = beta + mmax, *lastc = theta + s + 1;
-    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)s * 6 * (size_t)mmax, &p));
+    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)s * 7 * (size_t)mmax, &p));
     double *tri = (double *)p;
     LzBufs b;
     TRY(lz_bufs(ctx, n, mmax, &b));
@@ -283,7 +289,7 @@ static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, dou
                          int *info_d)
 {
     void *p;
-    TRY(ws_get(ctx, WS_DINV, sizeof(double) * (size_t)cdiv(n, NB) * NB * NB, &p));
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     double *Dinv = (double *)p;
     *Dinv_out = Dinv;
     HIP_TRY(hipMemsetAsync(info_d, 0, sizeof(int), ctx->stream));
@@ -313,7 +319,7 @@ static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, dou
         sd.upper_only = 1;
         TRY(launch_gemm_f64(sd, ctx->stream));
     }
-    return 0;
+    return launch_make_m(B, ldb, n, Dinv, Dinv + nblk * NB * NB, ctx->stream);
 }
 
 static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
@@ -417,10 +423,10 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     const int64_t mmax = eff_max_steps(n, s, &o);
     const int64_t ldv = round_ld(n), nblk = cdiv(n, NB);
     size_t b = 0;
-    b += sizeof(double) * (size_t)nblk * NB * NB;                 // Dinv
+    b += 3 * sizeof(double) * (size_t)nblk * NB * NB;             // Dinv, M, M'
     b += sizeof(double) * (size_t)ldv * (size_t)(mmax + 1);       // V
     b += sizeof(double) * (size_t)(2 * mmax + 2 * s + 16);        // T
-    b += sizeof(double) * (size_t)s * 6 * (size_t)mmax;           // tridiagonal scratch
+    b += sizeof(double) * (size_t)s * 7 * (size_t)mmax;           // tridiagonal scratch
     b += sizeof(double) * (size_t)mmax * (size_t)s;               // S
     b += 2 * sizeof(double) * (size_t)ldv * (size_t)s;            // check blocks
     b += sizeof(double) * (size_t)nblk * nblk * NB;               // SYMV column partials
@@ -461,8 +467,8 @@ int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int tr
     TRY(ctl_reserve(ctx, n));
     double *Dinv;
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
-    if (trans == 0) return launch_trsv_n(U, ldu, n, Dinv, b, x, ctx->ctl_n, ctx->stream);
-    return launch_trsv_t(U, ldu, n, Dinv, b, x, ctx->ctl_t, ctx->stream);
+    if (trans == 0) return launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_n, ctx->stream);
+    return launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_t, ctx->stream);
 }
 
 int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)
@@ -535,7 +541,7 @@ int gsyeig_tridiag_eig(gsyeig_ctx *ctx, int64_t m, const double *alpha, const do
     void *p;
     TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * nwant + 16), &p));
     double *th = (double *)p, *lastc = th + nwant + 1;
-    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)nwant * 6 * (size_t)m, &p));
+    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)nwant * 7 * (size_t)m, &p));
     double *tri = (double *)p;
     TRY(launch_tri_bisect(alpha, beta ? beta : alpha, m, nwant, which, th, ctx->stream));
     if (S) TRY(launch_tri_vectors(alpha, beta ? beta : alpha, m, nwant, th, S, lds, tri, 1, lastc,

@@ -39,7 +39,7 @@ __host__ __device__ inline double *ctl_stage(PCtl *c)
 }
 
 enum WsSlot {
-    WS_DINV = 0,   // n x NB FP64: inverses of the diagonal blocks of U
+    WS_DINV = 0,   // 3 n x NB FP64: Dinv_i = U_ii^-1, M_i, M'_i (chain blocks of the solves)
     WS_TMP1,       // n FP64
     WS_TMP2,       // n FP64
     WS_SYMV_PR,    // SYMV row partials
@@ -103,10 +103,13 @@ struct GemmDesc {
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
-int launch_trsv_n(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
-                  double *x, PCtl *ctl, hipStream_t st);
-int launch_trsv_t(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
-                  double *x, PCtl *ctl, hipStream_t st);
+// M holds [M_i | M'_i] for all blocks (see launch_make_m)
+int launch_make_m(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *M,
+                  hipStream_t st);
+int launch_trsv_n(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *M,
+                  const double *b, double *x, PCtl *ctl, hipStream_t st);
+int launch_trsv_t(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *M,
+                  const double *b, double *x, PCtl *ctl, hipStream_t st);
 int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x,
                 double *y);
 int launch_potrf_diag(double *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,

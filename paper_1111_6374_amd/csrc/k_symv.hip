@@ -88,19 +88,32 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A
     }
 }
 
-// y_K = sum of the row parts of block row K + column parts of tiles (I, K), I < K.
-__global__ __launch_bounds__(64) void k_symv_reduce(const double *__restrict__ Pr,
-                                                    const double *__restrict__ Pc, int nblk,
-                                                    int maxch, int64_t n, double *__restrict__ y)
+// y_K = sum of the row parts of block row K + column parts of tiles (I, K),
+// I < K.  256 threads: thread (q, t) sums every 4th partial of element t,
+// reading 2 KB of contiguous partials per step; a fixed-order LDS fold ends it.
+__global__ __launch_bounds__(256) void k_symv_reduce(const double *__restrict__ Pr,
+                                                     const double *__restrict__ Pc, int nblk,
+                                                     int maxch, int64_t n, double *__restrict__ y)
 {
-    const int K = blockIdx.x, t = threadIdx.x;
+    __shared__ double sred[4][NB];
+    const int K = blockIdx.x, t = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int nch = (nblk - K + SYMV_CH - 1) / SYMV_CH;
     double s = 0.0;
-    for (int ch = 0; ch < nch; ++ch) s += Pr[((int64_t)K * maxch + ch) * NB + t];
+    for (int ch = q; ch < nch; ch += 4) s += Pr[((int64_t)K * maxch + ch) * NB + t];
     const double *pc = Pc + (int64_t)K * nblk * NB + t;
-    for (int I = 0; I < K; ++I) s += pc[(int64_t)I * NB];
-    const int64_t row = (int64_t)K * NB + t;
-    if (row < n) y[row] = s;
+    int I = q;
+    for (; I + 12 < K; I += 16) {
+        const double a0 = pc[(int64_t)I * NB], a1 = pc[(int64_t)(I + 4) * NB];
+        const double a2 = pc[(int64_t)(I + 8) * NB], a3 = pc[(int64_t)(I + 12) * NB];
+        s += (a0 + a1) + (a2 + a3);
+    }
+    for (; I < K; I += 4) s += pc[(int64_t)I * NB];
+    sred[q][t] = s;
+    __syncthreads();
+    if (q == 0) {
+        const int64_t row = (int64_t)K * NB + t;
+        if (row < n) y[row] = (sred[0][t] + sred[1][t]) + (sred[2][t] + sred[3][t]);
+    }
 }
 
 }  // namespace
@@ -129,7 +142,7 @@ int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const 
                        lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr,
                        (double *)pc);
     if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
-    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(64), 0, ctx->stream, (const double *)pr,
+    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
                        (const double *)pc, nblk, maxch, n, y);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }

@@ -15,13 +15,22 @@
 //     agent-scope atomic store and a consumer polls exactly the values it
 //     needs until they are not the sentinel.  Every value carries its own
 //     readiness, so no flags, fences or cache write-backs sit on the chain;
-//   * the 64x64 diagonal solve is a product with Dinv_I = U_II^-1 held in
-//     registers.  The last workgroup to retire restores the sentinels.
+//   * the block solve is split around the chain: with Dinv_I = U_II^-1 and
+//     M_I = Dinv_I U_{I,I+1} precomputed, y_I = Dinv_I (b_I - sum over the
+//     far tiles) is formed while block I+1 is still being solved, and once
+//     x_{I+1} arrives each wave finishes its own 4 rows of
+//     x_I = y_I - M_I x_{I+1} with no workgroup barrier on the chain (the
+//     U^-T sweep uses Dinv_I^T and M'_I = Dinv_I^T U_{I-1,I}^T the same way).
+//     The last workgroup to retire restores the sentinels.
 //
-// Tile lane map (64x64 tile, 4 wave64s): wave w owns tile columns
-// 16w..16w+15, lane l reads column 16w + (l & 15) of rows (l >> 4) + 4q,
-// q = 0..15 -- four 128-byte row segments per load instruction.
+// Layout: 1024 threads = 16 wave64s per block.  In a 64x64 tile, wave w owns
+// rows 4w..4w+3 and lane l owns column l, so every load instruction reads one
+// full 512-byte row segment.  Tiles are consumed in groups of GRP: the
+// values of a group are polled while the next group's tiles stream in, and
+// all addresses are clamped in range so no branch separates the two.
 #include "internal.h"
+
+#define GRP 4
 
 namespace {
 
@@ -39,7 +48,7 @@ __device__ __forceinline__ void st_bits(double *p, unsigned long long v)
 
 // Finish a poll started with ld_bits: spin (bounded) while the value is the
 // sentinel.  An expired wait records an error and yields 0.
-__device__ __forceinline__ double settle(unsigned long long v, const double *p, unsigned *err)
+__device__ __noinline__ double settle_slow(unsigned long long v, const double *p, unsigned *err)
 {
     unsigned it = 0;
     while (v == STAGE_SENTINEL) {
@@ -47,10 +56,33 @@ __device__ __forceinline__ double settle(unsigned long long v, const double *p, 
             __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return 0.0;
         }
-        __builtin_amdgcn_s_sleep(1);
         v = ld_bits(p);
     }
     return __longlong_as_double((long long)v);
+}
+
+__device__ __forceinline__ double settle(unsigned long long v, const double *p, unsigned *err)
+{
+    if (__builtin_expect(v != STAGE_SENTINEL, 1)) return __longlong_as_double((long long)v);
+    return settle_slow(v, p, err);
+}
+
+__device__ __forceinline__ double rdlane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
 }
 
 // Chain position of this workgroup.  A counter left inconsistent by an
@@ -87,171 +119,288 @@ __device__ void retire(PCtl *ctl, double *stage, int64_t nstage, int nblk, int *
 }
 
 // ------------------------------------------------------------------ KI1
-__global__ __launch_bounds__(256) void k_trsv_n(const double *__restrict__ U, int64_t ldu,
-                                                int64_t n, int nblk,
-                                                const double *__restrict__ Dinv,
-                                                const double *b, double *x, PCtl *ctl)
+__global__ __launch_bounds__(1024) void k_trsv_n(const double *__restrict__ U, int64_t ldu,
+                                                 int64_t n, int nblk,
+                                                 const double *__restrict__ Dinv,
+                                                 const double *__restrict__ Mn,
+                                                 const double *b, double *x, PCtl *ctl)
 {
     __shared__ int s_blk, s_last;
-    __shared__ double s_part[4][NB];
     __shared__ double s_r[NB];
+    __shared__ double s_y[NB];
     double *stage = ctl_stage(ctl);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     if (tid == 0) s_blk = nblk - 1 - take_ticket(ctl, nblk);
     __syncthreads();
     const int I = s_blk;
     const int64_t r0 = (int64_t)I * NB;
-    const int c = 16 * w + (lane & 15);
-    const int rg = lane >> 4;
+    const bool has_next = I < nblk - 1;
 
-    // Dinv row for the diagonal solve: thread t -> row t>>2, columns (t&3)*16..+15
-    const int drow = tid >> 2, dq = tid & 3;
-    double dinv[16];
+    // Dinv_I: thread t -> row t>>4, columns (t&15)*4..+3;  M_I: rows 4w..4w+3, column l
+    const int drow = tid >> 4, dq = tid & 15;
+    double dinv[4], mrow[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) dinv[k] = Dinv[(int64_t)I * NB * NB + drow * NB + dq * 16 + k];
+    for (int k = 0; k < 4; ++k) dinv[k] = Dinv[(int64_t)I * NB * NB + drow * NB + dq * 4 + k];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mrow[r] = has_next ? Mn[(int64_t)I * NB * NB + (4 * w + r) * NB + l] : 0.0;
 
-    double acc[16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ntile = nblk - 2 - I;  // far tiles j = nblk-1 .. I+2
+    if (ntile > 0) {
+        // rows 4w..4w+3 of block I all exist (block I is not the last one)
+        const double *Ur = U + (r0 + 4 * w) * ldu;
+        const int64_t cmax = n - 1;
+        // tile index t (0-based from the right) -> column of this lane, clamped
+        auto colof = [&](int t) {
+            const int j = (t < ntile) ? nblk - 1 - t : I + 2;
+            const int64_t cc = (int64_t)j * NB + l;
+            return cc < cmax ? cc : cmax;
+        };
+        double cur[GRP][4], nxt[GRP][4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-
-    const double *Urow = U + (r0 + rg) * ldu;
-    auto load_tile = [&](double *t, int j) {
-        const int64_t col = (int64_t)j * NB + c;
+        for (int g = 0; g < GRP; ++g) {
+            const int64_t cc = colof(g);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const bool ok = (r0 + rg + 4 * q < n) && (col < n);
-            t[q] = ok ? Urow[(int64_t)(4 * q) * ldu + col] : 0.0;
+            for (int r = 0; r < 4; ++r) cur[g][r] = Ur[(int64_t)r * ldu + cc];
         }
-    };
-    double a[16];
-    if (nblk - 1 > I) load_tile(a, nblk - 1);
-    for (int j = nblk - 1; j > I; --j) {
-        const int64_t col = (int64_t)j * NB + c;
-        const bool colok = col < n;
-        const unsigned long long v = colok ? ld_bits(stage + col) : 0ull;
-        double an[16];
-        if (j - 1 > I) load_tile(an, j - 1);
-        const double xj = colok ? settle(v, stage + col, &ctl->err) : 0.0;
+        for (int t0 = 0; t0 < ntile; t0 += GRP) {
+            unsigned long long v[GRP];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = fma(a[q], xj, acc[q]);
-        if (j - 1 > I) {
+            for (int g = 0; g < GRP; ++g) v[g] = ld_bits(stage + colof(t0 + g));
 #pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = an[q];
+            for (int g = 0; g < GRP; ++g) {
+                const int64_t cc = colof(t0 + GRP + g);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) nxt[g][r] = Ur[(int64_t)r * ldu + cc];
+            }
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+                const int t = t0 + g;
+                const int64_t col = (int64_t)(nblk - 1 - t) * NB + l;
+                const bool live = (t < ntile) && (col < n);
+                const double xv = settle(v[g], stage + colof(t), &ctl->err);
+                const double xj = live ? xv : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = fma(cur[g][r], xj, acc[r]);
+            }
+#pragma unroll
+            for (int g = 0; g < GRP; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cur[g][r] = nxt[g][r];
         }
     }
-    // row sums: reduce over the 16 lanes sharing a row, then over the 4 waves
+    // y_I = Dinv_I (b_I - far row sums)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        double v = acc[q];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        acc[q] = v;
-    }
-    if ((lane & 15) == 0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) s_part[w][rg + 4 * q] = acc[q];
+    for (int r = 0; r < 4; ++r) acc[r] = wave_sum(acc[r]);
+    if (l < 4) {
+        const int row = 4 * w + l;
+        const double a = (l == 0) ? acc[0] : (l == 1) ? acc[1] : (l == 2) ? acc[2] : acc[3];
+        s_r[row] = ((r0 + row < n) ? b[r0 + row] : 0.0) - a;
     }
     __syncthreads();
-    if (tid < NB) {
-        const int64_t row = r0 + tid;
-        const double bi = (row < n) ? b[row] : 0.0;
-        s_r[tid] = bi - (s_part[0][tid] + s_part[1][tid] + s_part[2][tid] + s_part[3][tid]);
-    }
-    __syncthreads();
-    double v = 0.0;
+    double y = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v = fma(dinv[k], s_r[dq * 16 + k], v);
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (dq == 0 && r0 + drow < n) {
-        st_bits(stage + r0 + drow, (unsigned long long)__double_as_longlong(v));
-        x[r0 + drow] = v;
+    for (int k = 0; k < 4; ++k) y = fma(dinv[k], s_r[dq * 4 + k], y);
+    y += __shfl_xor(y, 1);
+    y += __shfl_xor(y, 2);
+    y += __shfl_xor(y, 4);
+    y += __shfl_xor(y, 8);
+    if (dq == 0) s_y[drow] = y;
+    __syncthreads();
+    // chain: each wave finishes rows 4w..4w+3 of x_I = y_I - M_I x_{I+1}
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (has_next) {
+        const int64_t cn = (int64_t)(I + 1) * NB + l;
+        const int64_t cc = cn < n ? cn : n - 1;
+        const double xv = settle(ld_bits(stage + cc), stage + cc, &ctl->err);
+        const double xn = (cn < n) ? xv : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[r] = wave_sum(mrow[r] * xn);
+    }
+    if (l < 4) {
+        const int row = 4 * w + l;
+        const double p = (l == 0) ? part[0] : (l == 1) ? part[1] : (l == 2) ? part[2] : part[3];
+        if (r0 + row < n) {
+            const double xi = s_y[row] - p;
+            st_bits(stage + r0 + row, (unsigned long long)__double_as_longlong(xi));
+            x[r0 + row] = xi;
+        }
     }
     retire(ctl, stage, n, nblk, &s_last);
 }
 
 // ------------------------------------------------------------------ KI3
-__global__ __launch_bounds__(256) void k_trsv_t(const double *__restrict__ U, int64_t ldu,
-                                                int64_t n, int nblk,
-                                                const double *__restrict__ Dinv,
-                                                const double *b, double *x, PCtl *ctl)
+__global__ __launch_bounds__(1024) void k_trsv_t(const double *__restrict__ U, int64_t ldu,
+                                                 int64_t n, int nblk,
+                                                 const double *__restrict__ Dinv,
+                                                 const double *__restrict__ Mt,
+                                                 const double *b, double *x, PCtl *ctl)
 {
     __shared__ int s_blk, s_last;
+    __shared__ double s_part[16][NB];
     __shared__ double s_r[NB];
+    __shared__ double s_y[NB];
     double *stage = ctl_stage(ctl);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     if (tid == 0) s_blk = take_ticket(ctl, nblk);
     __syncthreads();
     const int I = s_blk;
     const int64_t c0 = (int64_t)I * NB;
-    const int c = 16 * w + (lane & 15);
-    const int rg = lane >> 4;
-    const int64_t col = c0 + c;
+    const int64_t col = c0 + l;
     const bool colok = col < n;
+    const int64_t colc = colok ? col : n - 1;
 
-    // Dinv^T product: thread t -> output column t>>2, rows (t&3)*16..+15
-    const int dcol = tid >> 2, dq = tid & 3;
-    double dinv[16];
+    // Dinv_I^T: thread t -> output column t>>4, rows (t&15)*4..+3; M'_I: rows 4w..4w+3, column l
+    const int dcol = tid >> 4, dq = tid & 15;
+    double dinv[4], mrow[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) dinv[k] = Dinv[(int64_t)I * NB * NB + (dq * 16 + k) * NB + dcol];
+    for (int k = 0; k < 4; ++k) dinv[k] = Dinv[(int64_t)I * NB * NB + (dq * 4 + k) * NB + dcol];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mrow[r] = (I > 0) ? Mt[(int64_t)I * NB * NB + (4 * w + r) * NB + l] : 0.0;
 
-    // rows of U above block I are complete 64-row blocks (J < I), so only the
-    // column can be out of range.
-    auto load_tile = [&](double *t, int j) {
-        const double *Ut = U + ((int64_t)j * NB + rg) * ldu + col;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) t[q] = colok ? Ut[(int64_t)(4 * q) * ldu] : 0.0;
-    };
     double acc = 0.0;
-    double a[16];
-    if (I > 0) load_tile(a, 0);
-    for (int j = 0; j < I; ++j) {
-        const double *zs = stage + (int64_t)j * NB + rg;
-        unsigned long long v[16];
+    const int ntile = I - 1;  // far tiles j = 0 .. I-2
+    if (ntile > 0) {
+        // tile j covers rows j*64 + 4w + r (all < n since j < I) and column col
+        auto rowof = [&](int t) { return (int64_t)((t < ntile) ? t : ntile - 1) * NB + 4 * w; };
+        double cur[GRP][4], nxt[GRP][4];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = ld_bits(zs + 4 * q);
-        double an[16];
-        if (j + 1 < I) load_tile(an, j + 1);
+        for (int g = 0; g < GRP; ++g) {
+            const int64_t rr = rowof(g);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma(a[q], settle(v[q], zs + 4 * q, &ctl->err), acc);
-        if (j + 1 < I) {
+            for (int r = 0; r < 4; ++r) cur[g][r] = U[(rr + r) * ldu + colc];
+        }
+        for (int t0 = 0; t0 < ntile; t0 += GRP) {
+            // lane p < 16 polls value r = p & 3 of tile g = p >> 2 of the group;
+            // the other lanes repeat those addresses
+            const int p = l & 15;
+            const int64_t prow = rowof(t0 + (p >> 2)) + (p & 3);
+            const unsigned long long pv = ld_bits(stage + prow);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = an[q];
+            for (int g = 0; g < GRP; ++g) {
+                const int64_t rr = rowof(t0 + GRP + g);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) nxt[g][r] = U[(rr + r) * ldu + colc];
+            }
+            const double zmine = settle(pv, stage + prow, &ctl->err);
+#pragma unroll
+            for (int g = 0; g < GRP; ++g) {
+                const bool live = (t0 + g < ntile);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double zv = rdlane(zmine, g * 4 + r);
+                    acc = fma(cur[g][r], live ? zv : 0.0, acc);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < GRP; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cur[g][r] = nxt[g][r];
         }
     }
-    // column sums: reduce over the 4 row groups of the wave
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    if (rg == 0) s_r[c] = (colok ? b[col] : 0.0) - acc;
+    // y_I = Dinv_I^T (b_I - far column sums)
+    s_part[w][l] = acc;
     __syncthreads();
-    double v = 0.0;
+    if (tid < NB) {
+        double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v = fma(dinv[k], s_r[dq * 16 + k], v);
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    if (dq == 0 && c0 + dcol < n) {
-        st_bits(stage + c0 + dcol, (unsigned long long)__double_as_longlong(v));
-        x[c0 + dcol] = v;
+        for (int q = 0; q < 16; ++q) s += s_part[q][tid];
+        s_r[tid] = ((c0 + tid < n) ? b[c0 + tid] : 0.0) - s;
+    }
+    __syncthreads();
+    double y = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y = fma(dinv[k], s_r[dq * 4 + k], y);
+    y += __shfl_xor(y, 1);
+    y += __shfl_xor(y, 2);
+    y += __shfl_xor(y, 4);
+    y += __shfl_xor(y, 8);
+    if (dq == 0) s_y[dcol] = y;
+    __syncthreads();
+    // chain: each wave finishes entries 4w..4w+3 of x_I = y_I - M'_I x_{I-1}
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (I > 0) {
+        const int64_t rp = (int64_t)(I - 1) * NB + l;  // block I-1 is complete
+        const double xp = settle(ld_bits(stage + rp), stage + rp, &ctl->err);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[r] = wave_sum(mrow[r] * xp);
+    }
+    if (l < 4) {
+        const int e = 4 * w + l;
+        const double p = (l == 0) ? part[0] : (l == 1) ? part[1] : (l == 2) ? part[2] : part[3];
+        if (c0 + e < n) {
+            const double xi = s_y[e] - p;
+            st_bits(stage + c0 + e, (unsigned long long)__double_as_longlong(xi));
+            x[c0 + e] = xi;
+        }
     }
     retire(ctl, stage, n, nblk, &s_last);
 }
 
+// M_i = Dinv_i U_{i,i+1} (i < nblk-1) and M'_i = Dinv_i^T U_{i-1,i}^T (i > 0),
+// 64x64 row-major each; entries that would touch columns >= n are zero.
+__global__ __launch_bounds__(256) void k_make_m(const double *__restrict__ U, int64_t ldu, int64_t n,
+                                                const double *__restrict__ Dinv, double *Mn,
+                                                double *Mt)
+{
+    __shared__ double d[NB][NB + 1];
+    __shared__ double t[NB][NB + 1];
+    const int i = blockIdx.x, nblk = gridDim.x;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 256) d[e / NB][e % NB] = Dinv[(int64_t)i * NB * NB + e];
+    // U_{i,i+1}: rows i*64+a, columns (i+1)*64+c
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int a = e / NB, c = e % NB;
+        const int64_t row = (int64_t)i * NB + a, cl = (int64_t)(i + 1) * NB + c;
+        t[a][c] = (i + 1 < nblk && row < n && cl < n) ? U[row * ldu + cl] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int a = e / NB, c = e % NB;
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s = fma(d[a][k], t[k][c], s);
+        Mn[(int64_t)i * NB * NB + e] = s;
+    }
+    __syncthreads();
+    // U_{i-1,i}: rows (i-1)*64+b, columns i*64+k
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int bb = e / NB, k = e % NB;
+        const int64_t row = (int64_t)(i - 1) * NB + bb, cl = (int64_t)i * NB + k;
+        t[bb][k] = (i > 0 && cl < n) ? U[row * ldu + cl] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int a = e / NB, bb = e % NB;
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s = fma(d[k][a], t[bb][k], s);
+        Mt[(int64_t)i * NB * NB + e] = s;
+    }
+}
+
 }  // namespace
 
-int launch_trsv_n(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
-                  double *x, PCtl *ctl, hipStream_t st)
+int launch_make_m(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *M,
+                  hipStream_t st)
 {
     const int nblk = (int)cdiv(n, NB);
-    hipLaunchKernelGGL(k_trsv_n, dim3(nblk), dim3(256), 0, st, U, ldu, n, nblk, Dinv, b, x, ctl);
+    hipLaunchKernelGGL(k_make_m, dim3(nblk), dim3(256), 0, st, U, ldu, n, Dinv, M,
+                       M + (int64_t)nblk * NB * NB);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
-int launch_trsv_t(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *b,
-                  double *x, PCtl *ctl, hipStream_t st)
+int launch_trsv_n(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *M,
+                  const double *b, double *x, PCtl *ctl, hipStream_t st)
 {
     const int nblk = (int)cdiv(n, NB);
-    hipLaunchKernelGGL(k_trsv_t, dim3(nblk), dim3(256), 0, st, U, ldu, n, nblk, Dinv, b, x, ctl);
+    hipLaunchKernelGGL(k_trsv_n, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, Dinv, M, b, x, ctl);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+int launch_trsv_t(const double *U, int64_t ldu, int64_t n, const double *Dinv, const double *M,
+                  const double *b, double *x, PCtl *ctl, hipStream_t st)
+{
+    const int nblk = (int)cdiv(n, NB);
+    hipLaunchKernelGGL(k_trsv_t, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, Dinv,
+                       M + (int64_t)nblk * NB * NB, b, x, ctl);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
