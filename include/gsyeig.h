@@ -113,6 +113,15 @@ int gsyeig_create(gsyeig_ctx **ctx, void *hip_stream);
 /* Wait for the context's stream and free everything the context owns. */
 int gsyeig_destroy(gsyeig_ctx *ctx);
 
+/* Chain granularity of the triangular solves KI1/KI3 for subsequent calls
+ * on this context: 64 = one 64-row diagonal block per chain link (each
+ * link multiplies by the inverse of a 64x64 diagonal block); 512 (default) =
+ * 512-row super-blocks applied through their explicit inverses (8x fewer
+ * chain links; the forward error then carries the condition number of the
+ * 512x512 diagonal blocks of U).  Returns 0, -1 (NULL ctx), -2 (other sizes).
+ * Host-only setting; takes effect at the next factorisation or solve. */
+int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
+
 /* Bytes of device workspace gsyeig_solve needs for (n, s, opts) (host-only
  * arithmetic; no GPU call). */
 int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes);

@@ -36,13 +36,16 @@ int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out)
     return 0;
 }
 
-static size_t ctl_bytes(int64_t rows) { return PCTL_STAGE_OFFSET + sizeof(double) * (size_t)rows; }
+// counters, then two staging vectors of `rows` entries (solved values x and,
+// for the super-block solves, the partial right-hand sides r')
+static size_t ctl_bytes(int64_t rows) { return PCTL_STAGE_OFFSET + 2 * sizeof(double) * (size_t)rows; }
+static double *ctl_rstage(gsyeig_ctx *ctx, PCtl *c) { return ctl_stage(c) + ctx->ctl_rows; }
 
 // zero counters, staging entries all STAGE_SENTINEL (all-ones bytes)
 static int ctl_init(gsyeig_ctx *ctx, PCtl *c, int64_t rows)
 {
     HIP_TRY(hipMemsetAsync(c, 0, PCTL_STAGE_OFFSET, ctx->stream));
-    HIP_TRY(hipMemsetAsync(ctl_stage(c), 0xFF, sizeof(double) * (size_t)rows, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctl_stage(c), 0xFF, 2 * sizeof(double) * (size_t)rows, ctx->stream));
     return 0;
 }
 
@@ -119,13 +122,44 @@ static int64_t round_ld(int64_t n) { return cdiv(n, 64) * 64; }
 static size_t tri_aux_bytes(int64_t n) { return 3 * sizeof(double) * (size_t)cdiv(n, NB) * NB * NB; }
 static const double *aux_m(const double *Dinv, int64_t n) { return Dinv + cdiv(n, NB) * NB * NB; }
 
+static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv);
+
+// Side data of the factor for the solves: M blocks always, super-block data
+// when the context uses super-block solves.
+static int prepare_solves(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double *Dinv)
+{
+    TRY(launch_make_m(U, ldu, n, Dinv, Dinv + cdiv(n, NB) * NB * NB, ctx->stream));
+    if (ctx->trsv_block == 64) return 0;
+    void *p;
+    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    return launch_make_sb(U, ldu, n, Dinv, (double *)p, ctx->stream);
+}
+
 static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv)
 {
     void *p;
     TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     *Dinv = (double *)p;
     TRY(launch_diag_inv(U, ldu, n, *Dinv, ctx->stream));
-    return launch_make_m(U, ldu, n, *Dinv, *Dinv + cdiv(n, NB) * NB * NB, ctx->stream);
+    return prepare_solves(ctx, n, U, ldu, *Dinv);
+}
+
+static int solve_n(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
+                   const double *b, double *x)
+{
+    if (ctx->trsv_block == 64)
+        return launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_n, ctx->stream);
+    return launch_trsv_sb_n(U, ldu, n, (const double *)ctx->ws[WS_SB], b, x,
+                            ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n, ctx->stream);
+}
+
+static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
+                   const double *b, double *x)
+{
+    if (ctx->trsv_block == 64)
+        return launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_t, ctx->stream);
+    return launch_trsv_sb_t(U, ldu, n, (const double *)ctx->ws[WS_SB], b, x,
+                            ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t, ctx->stream);
 }
 
 // Sampled kernel timing: events recorded around KI1/KI2/KI3 on the stream;
@@ -150,11 +184,11 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, co
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
-    TRY(launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), w, tmp, ctx->ctl_n, ctx->stream));
+    TRY(solve_n(ctx, n, U, ldu, Dinv, w, tmp));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
     TRY(launch_symv(ctx, n, A, lda, tmp, z));
     if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
-    TRY(launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), z, z, ctx->ctl_t, ctx->stream));
+    TRY(solve_t(ctx, n, U, ldu, Dinv, z, z));
     if (sample) {
         HIP_TRY(hipEventRecord(e[3], ctx->stream));
         ctx->npev += 4;
@@ -319,7 +353,7 @@ static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, dou
         sd.upper_only = 1;
         TRY(launch_gemm_f64(sd, ctx->stream));
     }
-    return launch_make_m(B, ldb, n, Dinv, Dinv + nblk * NB * NB, ctx->stream);
+    return prepare_solves(ctx, n, B, ldb, Dinv);
 }
 
 static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
@@ -379,6 +413,7 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
     memset(ctx, 0, sizeof(*ctx));
     ctx->stream = (hipStream_t)hip_stream;
     ctx->symv_map_n = -1;
+    ctx->trsv_block = 512;
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     if (hipHostMalloc(&ctx->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
@@ -413,6 +448,14 @@ int gsyeig_destroy(gsyeig_ctx *ctx)
     return 0;
 }
 
+int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
+{
+    if (!ctx) return -1;
+    if (rows != 64 && rows != trsv_sb_rows()) return -2;
+    ctx->trsv_block = rows;
+    return 0;
+}
+
 int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes)
 {
     if (n < 1) return -1;
@@ -430,6 +473,7 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     b += sizeof(double) * (size_t)mmax * (size_t)s;               // S
     b += 2 * sizeof(double) * (size_t)ldv * (size_t)s;            // check blocks
     b += sizeof(double) * (size_t)nblk * nblk * NB;               // SYMV column partials
+    b += trsv_sb_bytes(n);                                        // super-block solve data
     b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
     b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
     *bytes = b;
@@ -467,8 +511,7 @@ int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int tr
     TRY(ctl_reserve(ctx, n));
     double *Dinv;
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
-    if (trans == 0) return launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_n, ctx->stream);
-    return launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_t, ctx->stream);
+    return trans == 0 ? solve_n(ctx, n, U, ldu, Dinv, b, x) : solve_t(ctx, n, U, ldu, Dinv, b, x);
 }
 
 int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)

@@ -54,6 +54,7 @@ enum WsSlot {
     WS_Y2,
     WS_BDIAG,      // saved diagonal of B
     WS_SYMVMAP,    // SYMV work list
+    WS_SB,         // super-block solve data: Uinv, Uinv^T, N, N' (SB x SB per super-block)
     WS_COUNT
 };
 
@@ -64,7 +65,8 @@ struct gsyeig_ctx {
     size_t ws_bytes[WS_COUNT];
     PCtl *ctl_n;        // persistent-kernel control blocks (+flags)
     PCtl *ctl_t;
-    int64_t ctl_rows;   // staging capacity (rows) of each control block
+    int64_t ctl_rows;   // staging capacity (rows) of each staging vector
+    int64_t trsv_block; // 64: chained 64-row solves; 512: super-block solves
     int64_t symv_map_n; // n for which WS_SYMVMAP is valid
     int64_t symv_items;
     void *host_pinned;  // small pinned host staging area
@@ -103,6 +105,15 @@ struct GemmDesc {
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
+// super-block solves (k_trsv_sb.hip); sb = [Uinv | Uinv^T | N | N']
+int64_t trsv_sb_rows();
+size_t trsv_sb_bytes(int64_t n);
+int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
+                   hipStream_t st);
+int launch_trsv_sb_n(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                     double *x, double *rstage, PCtl *ctl, hipStream_t st);
+int launch_trsv_sb_t(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                     double *x, double *rstage, PCtl *ctl, hipStream_t st);
 // M holds [M_i | M'_i] for all blocks (see launch_make_m)
 int launch_make_m(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *M,
                   hipStream_t st);

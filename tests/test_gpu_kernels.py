@@ -95,11 +95,13 @@ def test_potrf_leading_dimension(gs, ctx, torch, orc):
 
 
 # --------------------------------------------------------------- KI1 / KI3
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 1000, 4097])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 513, 1000, 1025, 4097])
 @pytest.mark.parametrize("trans", [0, 1])
-def test_trsv_matches_oracle(gs, ctx, torch, orc, n, trans):
-    say("trsv", n, trans)
-    d = gen.known_spectrum(n, seed=104, stream=(n,)) if n <= 1000 else None
+@pytest.mark.parametrize("block", [64, 512])
+def test_trsv_matches_oracle(gs, ctx, torch, orc, n, trans, block):
+    say("trsv", n, trans, block)
+    assert gs.gsyeig_set_trsv_block(ctx, block) == 0
+    d = gen.known_spectrum(n, seed=104, stream=(n,)) if n <= 600 else None
     U = d["U"] if d else gen.factor_U(n, gen.rng(104, n))
     b = gen.rng(105, n).standard_normal(n)
     Ud, bd = dev(torch, U), dev(torch, b)
@@ -115,8 +117,10 @@ def test_trsv_matches_oracle(gs, ctx, torch, orc, n, trans):
         assert np.array_equal(host(bd2), x)
 
 
-def test_trsv_bidiagonal_closed_form(gs, ctx, torch):
-    n = 333
+@pytest.mark.parametrize("block", [64, 512])
+def test_trsv_bidiagonal_closed_form(gs, ctx, torch, block):
+    assert gs.gsyeig_set_trsv_block(ctx, block) == 0
+    n = 1333
     U = np.eye(n) - np.eye(n, k=1)
     b = gen.rng(106).standard_normal(n)
     Ud, bd = dev(torch, U), dev(torch, b)
@@ -166,9 +170,11 @@ def test_symv_rank_one(gs, ctx, torch):
 
 
 # --------------------------------------------------------------- KI1-KI3
-@pytest.mark.parametrize("n", [65, 500])
-def test_apply_op_matches_oracle_and_known_c(gs, ctx, torch, orc, n):
-    say("apply_op", n)
+@pytest.mark.parametrize("n", [65, 500, 1600])
+@pytest.mark.parametrize("block", [64, 512])
+def test_apply_op_matches_oracle_and_known_c(gs, ctx, torch, orc, n, block):
+    say("apply_op", n, block)
+    assert gs.gsyeig_set_trsv_block(ctx, block) == 0
     d = gen.known_spectrum(n, seed=112, stream=(n,))
     w = gen.rng(113, n).standard_normal(n)
     zd = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -180,9 +186,10 @@ def test_apply_op_matches_oracle_and_known_c(gs, ctx, torch, orc, n):
 
 
 # --------------------------------------------------------------- KI4
-@pytest.mark.parametrize("n,k", [(300, 20), (129, 60)])
+@pytest.mark.parametrize("n,k", [(300, 20), (129, 60), (1100, 30)])
 def test_lanczos_recurrence_matches_oracle(gs, ctx, torch, orc, n, k):
     say("lanczos_run", n, k)
+    assert gs.gsyeig_set_trsv_block(ctx, 512) == 0
     d = gen.known_spectrum(n, seed=114, stream=(n,))
     v0 = gen.splitmix64_uniform(n, 17)
     a_ref, b_ref, W_ref = orc.lanczos(d["A"], d["U"], v0, k)

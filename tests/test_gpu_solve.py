@@ -65,9 +65,11 @@ def align(X, Xref):
     return sgn[:, None] * Xref
 
 
-@pytest.mark.parametrize("n,s", [(512, 10), (333, 7), (130, 13), (64, 5)])
-def test_solve_known_spectrum_vs_oracle(torch, solver, orc, n, s):
-    say("solve-known", n, s)
+@pytest.mark.parametrize("n,s,block", [(512, 10, 512), (512, 10, 64), (333, 7, 512), (130, 13, 512),
+                                       (64, 5, 512), (1500, 12, 512), (1500, 12, 64)])
+def test_solve_known_spectrum_vs_oracle(torch, solver, orc, gs, n, s, block):
+    say("solve-known", n, s, block)
+    assert gs.gsyeig_set_trsv_block(solver.ctx, block) == 0
     d = gen.known_spectrum(n, seed=6374, stream=(0, n))
     lam, X, info = run(torch, solver, d["A"], d["B"], s)
     assert info["rc"] == 0, info
