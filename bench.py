@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 CONFIGS = {
     0: dict(n=512, s=10, law="spaced", label="known-spectrum pencil n=512 s=10, FP64 single-vector KI"),
     1: dict(n=16384, s=100, law="spaced", label="known-spectrum pencil n=16384 s=100, FP64 single-vector KI"),
+    4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n), FP64"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -56,6 +57,8 @@ def main():
     ap.add_argument("--config", type=int, default=1, choices=sorted(CONFIGS))
     ap.add_argument("--profile-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--instances", type=int, default=512, help="instances for --config 4")
+    ap.add_argument("--streams", type=int, default=8, help="worker streams for --config 4")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -71,6 +74,8 @@ def main():
     import paper_1111_6374_amd as gs
 
     cfg = CONFIGS[args.config]
+    if args.config == 4:
+        return bench_batched(args, cfg)
     n, s = cfg["n"], cfg["s"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -158,6 +163,85 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, cfg):
+    """Many uneven instances: the batched entry point vs a loop of single solves."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1111_6374_amd as gs
+
+    dev = torch.device("cuda:0")
+    g = gen.rng(gen.BASE_SEED + 4, 0)
+    sizes = [int(v) for v in g.integers(256, 4097, size=args.instances)]
+    ss = [int(math.ceil(0.05 * n)) for n in sizes]
+    log(f"generating {len(sizes)} instances, sum n^3 = {sum(n**3 for n in sizes):.3e}")
+    t0 = time.perf_counter()
+    A, B0, lam_true = [], [], []
+    for i, n in enumerate(sizes):
+        d = gen.known_spectrum_device(n, "spaced", seed=gen.BASE_SEED + 4, stream=(4, i), device=dev,
+                                      keep_factors=False, rng_kind="torch")
+        A.append(d["A"])
+        B0.append(d["B"])
+        lam_true.append(np.sort(d["lam"])[: ss[i]])
+    B = [torch.empty_like(b) for b in B0]
+    Lam = [torch.empty(s, dtype=torch.float64, device=dev) for s in ss]
+    X = [torch.empty(s, n, dtype=torch.float64, device=dev) for s, n in zip(ss, sizes)]
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    solver = gs.Solver()
+
+    def restore():
+        for b, b0 in zip(B, B0):
+            b.copy_(b0)
+        torch.cuda.synchronize()
+
+    def batched():
+        restore()
+        t = time.perf_counter()
+        rc, status, infos = gs.gsyeig_solve_batched(solver.ctx, sizes, ss, A, sizes, B, sizes, None, Lam, X,
+                                                    sizes, nstreams=args.streams)
+        torch.cuda.synchronize()
+        if rc:
+            raise gs.GsyeigError("gsyeig_solve_batched", rc)
+        return time.perf_counter() - t, infos
+
+    for w in range(args.warmup):
+        dt, _ = batched()
+        log(f"warmup batched: {dt:.2f} s")
+    times = []
+    for k in range(args.steps):
+        dt, infos = batched()
+        times.append(dt)
+        log(f"step {k}: batched {dt:.2f} s")
+    # reference: the same instances as a loop of single-instance FP64 solves
+    restore()
+    t = time.perf_counter()
+    for i, n in enumerate(sizes):
+        rc, _ = gs.gsyeig_solve(solver.ctx, n, ss[i], A[i], n, B[i], n, None, Lam[i], X[i], n)
+        if rc:
+            raise gs.GsyeigError("gsyeig_solve", rc)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t
+    log(f"loop of single solves: {t_loop:.2f} s")
+    e_lam = max(float(np.max(np.abs(L.cpu().numpy() - lt))) for L, lt in zip(Lam, lam_true))
+    eta = max(i.eta_max for i in infos)
+    value = sum(times) / len(times)
+    out = {
+        "metric": "time-to-s-eigenpairs",
+        "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["label"], "instances": len(sizes), "sum_n": sum(sizes),
+                   "streams": args.streams, "prec": "fp64", "parallelism": "single-gpu"},
+        "loop_of_single_solves_s": t_loop, "batched_speedup": t_loop / value,
+        "lanczos_steps_total": int(sum(i.steps for i in infos)),
+        "parity": {"e_lambda_vs_known": e_lam, "eta_max": eta, "pass": bool(e_lam <= 1e-10 and eta <= 1e-10)},
+    }
+    solver.close()
     print(json.dumps(out), flush=True)
 
 

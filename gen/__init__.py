@@ -97,21 +97,30 @@ def known_spectrum(n: int, law: str = "spaced", seed: int = BASE_SEED, stream=(0
 
 
 def known_spectrum_device(n: int, law: str = "spaced", seed: int = BASE_SEED, stream=(0,),
-                          device="cuda", keep_factors: bool = True):
+                          device="cuda", keep_factors: bool = True, rng_kind: str = "numpy"):
     """Same instance law as ``known_spectrum`` assembled on a torch device.
 
-    The random draws (U, the Gaussian, lam) come from the same numpy streams as
-    the host version; only the O(n^3) assembly (QR and the products) runs on
-    the device with torch, so large n is generated in seconds.
+    rng_kind = "numpy": the random draws (U, the Gaussian, lam) come from the
+    same numpy streams as the host version; only the O(n^3) assembly (QR and
+    the products) runs on the device, so large n is generated in seconds.
+    rng_kind = "torch": the draws come from a torch generator on the device
+    seeded with (seed, stream) -- a different but equally seeded instance,
+    for workloads with many instances.
     """
     import torch
 
-    g = rng(seed, *stream)
-    U_h = factor_U(n, g)
-    U = torch.from_numpy(U_h).to(device)
-    del U_h
-    G = torch.from_numpy(g.standard_normal((n, n))).to(device)
-    lam_h = SPECTRA[law](n, g)
+    if rng_kind == "numpy":
+        g = rng(seed, *stream)
+        U = torch.from_numpy(factor_U(n, g)).to(device)
+        G = torch.from_numpy(g.standard_normal((n, n))).to(device)
+        lam_h = SPECTRA[law](n, g)
+    else:
+        tg = torch.Generator(device=device)
+        tg.manual_seed(int(np.random.SeedSequence([int(seed)] + [int(v) for v in stream]).generate_state(1)[0]))
+        U = torch.triu(torch.randn(n, n, generator=tg, device=device, dtype=torch.float64) / math.sqrt(n), 1)
+        U.diagonal().copy_(1.0 + torch.rand(n, generator=tg, device=device, dtype=torch.float64))
+        G = torch.randn(n, n, generator=tg, device=device, dtype=torch.float64)
+        lam_h = SPECTRA[law](n, rng(seed, *stream))
     Q, R = torch.linalg.qr(G)
     del G
     sgn = torch.sign(torch.diagonal(R))

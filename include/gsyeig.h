@@ -56,6 +56,7 @@ extern "C" {
 #define GSYEIG_EHIP 0x40000001
 #define GSYEIG_ESPIN 0x40000002
 #define GSYEIG_ENOMEM 0x40000003
+#define GSYEIG_MAX_STREAMS 16
 
 typedef struct gsyeig_ctx gsyeig_ctx;
 
@@ -206,6 +207,23 @@ int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
 int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
                  int64_t ldb, const gsyeig_opts *opts, double *Lambda, double *X, int64_t ldx,
                  gsyeig_info *info);
+
+/* Row a10 of the hot path (batched driver; the 3-5 %-of-the-spectrum regime
+ * of the paper's conclusions, Sec. 6): `count` independent pencils, each
+ * solved exactly as by gsyeig_solve.  All array arguments are HOST arrays of
+ * length count holding per-instance sizes and DEVICE pointers (A[i], B[i],
+ * Lambda[i], X[i]; same layouts and in-place behaviour as gsyeig_solve).
+ * Instances are processed largest first by `nstreams` (1..16) host threads,
+ * each with its own worker context and HIP stream owned by `ctx` (created
+ * on first use, freed by gsyeig_destroy).  status[i] receives instance i's
+ * return code; infos (host, may be NULL) its info.  Synchronises.  Returns
+ * 0 if every instance succeeded, else the first nonzero status in index
+ * order, or a negative code for an illegal batched argument. */
+int gsyeig_solve_batched(gsyeig_ctx *ctx, int64_t count, const int64_t *n, const int64_t *s,
+                         const double *const *A, const int64_t *lda, double *const *B,
+                         const int64_t *ldb, const gsyeig_opts *opts, double *const *Lambda,
+                         double *const *X, const int64_t *ldx, int64_t nstreams, int *status,
+                         gsyeig_info *infos);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
-    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block",
+    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_solve_batched",
 )
 
 
@@ -96,6 +96,10 @@ def lib():
             "gsyeig_check": ([P, I64, I64, P, I64, P, I64, P, P, P, I64, ctypes.POINTER(gsyeig_info)], I),
             "gsyeig_solve": ([P, I64, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, P, I64,
                               ctypes.POINTER(gsyeig_info)], I),
+            "gsyeig_solve_batched": ([P, I64, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(P),
+                                      ctypes.POINTER(I64), ctypes.POINTER(P), ctypes.POINTER(I64),
+                                      ctypes.POINTER(gsyeig_opts), ctypes.POINTER(P), ctypes.POINTER(P),
+                                      ctypes.POINTER(I64), I64, ctypes.POINTER(I), ctypes.POINTER(gsyeig_info)], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -200,6 +204,21 @@ def gsyeig_solve(ctx, n, s, A, lda, B, ldb, opts, Lambda, X, ldx):
     rc = lib().gsyeig_solve(ctx, n, s, _p(A), lda, _p(B), ldb, ctypes.byref(opts) if opts else None,
                             _p(Lambda), _p(X), ldx, ctypes.byref(info))
     return rc, info
+
+
+def gsyeig_solve_batched(ctx, n, s, A, lda, B, ldb, opts, Lambda, X, ldx, nstreams=8):
+    """Per-instance lists (host ints / device tensors or pointers).
+    Returns (rc, status list, list of gsyeig_info)."""
+    cnt = len(n)
+    I64A = ctypes.c_int64 * cnt
+    PA = ctypes.c_void_p * cnt
+    st = (ctypes.c_int * cnt)()
+    infos = (gsyeig_info * cnt)()
+    rc = lib().gsyeig_solve_batched(ctx, cnt, I64A(*n), I64A(*s), PA(*[_p(a) for a in A]), I64A(*lda),
+                                    PA(*[_p(b) for b in B]), I64A(*ldb),
+                                    ctypes.byref(opts) if opts else None, PA(*[_p(l) for l in Lambda]),
+                                    PA(*[_p(x) for x in X]), I64A(*ldx), nstreams, st, infos)
+    return rc, list(st), list(infos)
 
 
 # ------------------------------------------------------------------ torch convenience

@@ -6,6 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <numeric>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -433,6 +437,10 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
 int gsyeig_destroy(gsyeig_ctx *ctx)
 {
     if (!ctx) return -1;
+    for (int i = 0; i < ctx->nworkers; ++i) {
+        gsyeig_destroy(ctx->workers[i]);
+        (void)hipStreamDestroy(ctx->wstreams[i]);
+    }
     (void)hipStreamSynchronize(ctx->stream);
     for (int i = 0; i < WS_COUNT; ++i)
         if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
@@ -727,6 +735,72 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.t_ki3_ms_sum = ctx->prof_ms[2];
     if (info) *info = inf;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+}
+
+// Many independent pencils (row a10 of the hot path): instances are taken
+// largest-first from a shared counter by `nstreams` host threads, each
+// driving its own worker context on its own HIP stream, so small solves
+// overlap on the GPU.  Each instance runs exactly the single-solve path, so
+// its results are bitwise those of gsyeig_solve.
+int gsyeig_solve_batched(gsyeig_ctx *ctx, int64_t count, const int64_t *n, const int64_t *s,
+                         const double *const *A, const int64_t *lda, double *const *B,
+                         const int64_t *ldb, const gsyeig_opts *opts, double *const *Lambda,
+                         double *const *X, const int64_t *ldx, int64_t nstreams, int *status,
+                         gsyeig_info *infos)
+{
+    if (!ctx) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return 0;
+    if (!n) return -3;
+    if (!s) return -4;
+    if (!A) return -5;
+    if (!lda) return -6;
+    if (!B) return -7;
+    if (!ldb) return -8;
+    if (!Lambda) return -10;
+    if (!X) return -11;
+    if (!ldx) return -12;
+    if (nstreams < 1 || nstreams > GSYEIG_MAX_STREAMS) return -13;
+    if (!status) return -14;
+    // worker contexts, created once and kept by the parent context
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    while (ctx->nworkers < nstreams) {
+        hipStream_t st;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        gsyeig_ctx *w = nullptr;
+        int rc = gsyeig_create(&w, st);
+        if (rc) {
+            (void)hipStreamDestroy(st);
+            return rc;
+        }
+        ctx->wstreams[ctx->nworkers] = st;
+        ctx->workers[ctx->nworkers++] = w;
+    }
+    std::vector<int64_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return n[a] > n[b]; });
+    std::atomic<int64_t> next(0);
+    auto work = [&](int wi) {
+        gsyeig_ctx *w = ctx->workers[wi];
+        w->trsv_block = ctx->trsv_block;
+        if (hipSetDevice(ctx->device) != hipSuccess) return;
+        for (;;) {
+            const int64_t k = next.fetch_add(1);
+            if (k >= count) break;
+            const int64_t i = order[k];
+            gsyeig_info inf;
+            status[i] = gsyeig_solve(w, n[i], s[i], A[i], lda[i], B[i], ldb[i], opts, Lambda[i], X[i],
+                                     ldx[i], &inf);
+            if (infos) infos[i] = inf;
+        }
+    };
+    for (int64_t i = 0; i < count; ++i) status[i] = GSYEIG_EHIP;
+    std::vector<std::thread> th;
+    for (int wi = 0; wi < (int)nstreams; ++wi) th.emplace_back(work, wi);
+    for (auto &t : th) t.join();
+    for (int64_t i = 0; i < count; ++i)
+        if (status[i]) return status[i];
+    return 0;
 }
 
 }  // extern "C"

@@ -76,6 +76,9 @@ struct gsyeig_ctx {
     int npev;             // events recorded since the last harvest
     int64_t prof_samples;
     double prof_ms[3];
+    gsyeig_ctx *workers[GSYEIG_MAX_STREAMS];  // batched-solve worker contexts
+    hipStream_t wstreams[GSYEIG_MAX_STREAMS];
+    int nworkers;
 };
 
 // ---------------------------------------------------------------- helpers
