@@ -63,7 +63,10 @@ typedef struct gsyeig_ctx gsyeig_ctx;
 typedef enum { GSYEIG_FP64 = 0, GSYEIG_MIXED = 1 } gsyeig_prec;
 
 typedef struct {
-    int prec;              /* GSYEIG_FP64 (every step in FP64)                   */
+    int prec;              /* GSYEIG_FP64 (every step in FP64), or GSYEIG_MIXED:  */
+                           /*   FP32 copies of A and U for the Lanczos sweeps and */
+                           /*   the Cholesky trailing updates, then FP64          */
+                           /*   Rayleigh-Ritz refinement on the original (A, B)   */
     int block;             /* Lanczos block size; 1 = single-vector Lanczos       */
     int which;             /* 0 = s smallest (default), 1 = s largest             */
     int invert;            /* reserved (0): solve the inverse pencil (B, A)       */
@@ -77,6 +80,13 @@ typedef struct {
     const double *v0;      /* optional device start vector (n); overrides seed    */
     int64_t profile_every; /* 0 = off; else time KI1/KI2/KI3 with hipEvents on    */
                            /*   every profile_every-th Lanczos step (sampled)     */
+    /* mixed mode only */
+    double eta_tol;        /* refinement target: max per-pair backward error eta  */
+                           /*   over the wanted pairs (default 1e-10)             */
+    int64_t refine_iters;  /* most correction rounds (default 10)                 */
+    int64_t refine_inner;  /* MINRES steps per correction round (default 20)      */
+    int64_t guard;         /* extra Ritz vectors carried through the refinement   */
+                           /*   (0 = max(8, ceil(s/4)))                           */
 } gsyeig_opts;
 
 typedef struct {
@@ -98,6 +108,13 @@ typedef struct {
     double t_ki1_ms_sum;   /* sum over samples of the U^-1 sweep (KI1)         */
     double t_ki2_ms_sum;   /* ... of the A product (KI2)                       */
     double t_ki3_ms_sum;   /* ... of the U^-T sweep (KI3)                      */
+    /* mixed mode only */
+    double t_refine_ms;    /* FP64 refinement (Rayleigh-Ritz + corrections)    */
+    double eta_phase1;     /* max eta after the first FP64 Rayleigh-Ritz of the */
+                           /*   FP32-sweep Ritz vectors                         */
+    int64_t refine_iters;  /* correction rounds taken                           */
+    int64_t block_applies; /* FP32 block operator applications (block_cols wide)*/
+    int64_t block_cols;    /* width of the refinement block (s + guard)         */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */
@@ -127,10 +144,17 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
  * arithmetic; no GPU call). */
 int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes);
 
-/* GS1 (Eq. 2; Table 1): B = U^T U in place.  On return the upper triangle
- * (incl. diagonal) of B holds U; the strict lower triangle of B is left
- * untouched (so it still holds B's lower half).  `U_lowprec` must be NULL
- * (reserved).  Synchronises; returns 0 or the failing minor k > 0. */
+/* GS1 (Eq. 2; Table 1): B = U^T U.
+ * U_lowprec == NULL (FP64): in place; on return the upper triangle (incl.
+ * diagonal) of B holds U; the strict lower triangle of B is left untouched
+ * (so it still holds B's lower half).
+ * U_lowprec != NULL (mixed precision; required when opts->prec is
+ * GSYEIG_MIXED): B is only read; U~ is written as FP32 to U_lowprec (device,
+ * n x n row-major, leading dimension n, zeros below the diagonal).  The 64x64
+ * diagonal blocks are factored in FP64; the panel products and the trailing
+ * SYRK updates are FP32 matrix-core products with FP32 accumulation, so
+ * U~^T U~ = B + E with |E| of order n u_32 |U~|^T |U~|.
+ * Synchronises; returns 0 or the failing minor k > 0. */
 int gsyeig_potrf(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, const gsyeig_opts *opts,
                  void *U_lowprec);
 
@@ -181,6 +205,60 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
                    const double *U, int64_t ldu, const gsyeig_opts *opts, double *theta,
                    double *Y, int64_t ldy, int64_t *steps_out);
 
+/* KI1 / KI3 with U stored FP32 (the mixed-precision sweeps): x = U^-1 b or
+ * U^-T b for the FP32 upper-triangular U (row-major, ldu), FP64 b, x and
+ * FP64 arithmetic -- the exact solve with the FP32 matrix up to FP64
+ * rounding.  Uses 512-row super-block chain links.  x may alias b.
+ * Synchronises (checks the chained kernels' wait flags). */
+int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int trans, const double *b,
+                   double *x);
+
+/* KI2 with A stored FP32: y = A x (FP64 x, y and arithmetic; only the upper
+ * triangle of A is read).  Synchronises. */
+int gsyeig_symv_lp(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double *y);
+
+/* Block form of KI1 / KI3 used by the mixed-precision refinement:
+ * X = U^-1 V (trans = 0) or U^-T V (trans = 1) for k columns (n x k
+ * column-major), U FP32 upper triangular.  Products run on the FP32 matrix
+ * cores with FP32 accumulation over 512-row super-blocks, so X carries FP32
+ * rounding (relative error of order u_32 kappa(U)).  V is not modified.
+ * Synchronises. */
+int gsyeig_trsm_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int trans, int64_t k,
+                   const double *V, int64_t ldv, double *X, int64_t ldx);
+
+/* Dense symmetric eigensolver for the small projected matrices of the
+ * refinement (Rayleigh-Ritz, Section 2.3 step "eigenpairs of the projected
+ * matrix"): the nwant smallest (which = 0) or largest (which = 1)
+ * eigenpairs of the symmetric N x N matrix H (device, column-major, ldh;
+ * only read), N <= 2048, by Householder tridiagonalisation, Sturm bisection,
+ * inverse iteration (orthogonalised in clusters) and back-transformation.
+ * w (device, nwant) ascending; Q (device, N x nwant column-major, ldq)
+ * orthonormal.  Synchronises. */
+int gsyeig_syev_small(gsyeig_ctx *ctx, int64_t N, const double *H, int64_t ldh, int64_t nwant, int which,
+                      double *w, double *Q, int64_t ldq);
+
+/* FP64 refinement of the mixed-precision path (Rayleigh-Ritz on the
+ * ORIGINAL pencil of Eq. 1 with correction expansion; the paper ran FP64
+ * only, Section 3).  Starting block X0 (device, n x k column-major, k >= s,
+ * 2k <= 2048; e.g. U~^-1 times Ritz vectors of the FP32-sweep Lanczos):
+ *   repeat: B-orthonormalise; Rayleigh-Ritz with FP64 A X and B X;
+ *           R = A X - B X Theta; stop when the wanted s pairs have
+ *           eta_i = ||r_i|| / ((||A||_F + |theta_i| ||B||_F) ||x_i||)
+ *           <= opts->eta_tol; else opts->refine_inner MINRES steps on the
+ *           projected correction equation with the FP32 operator
+ *           C~ = U~^-T A~ U~^-1 (A~ = fl32(A)) and expand the basis;
+ * at most opts->refine_iters rounds.  U_lowprec: FP32 factor with
+ * U~^T U~ ~ B (e.g. from gsyeig_potrf in mixed mode).  Lambda (device, s,
+ * ascending) and X (device, n x s, B-orthonormal, sign-normalised as in
+ * gsyeig_solve) receive the wanted pairs (s smallest / largest per
+ * opts->which).  A, B and X0 are not modified.  *info (host, may be NULL):
+ * eta_max (= final max eta), eta_phase1 (after the first Rayleigh-Ritz),
+ * refine_iters, block_applies, block_cols, converged, t_refine_ms.
+ * Synchronises.  Returns 0 if max eta <= eta_tol, else GSYEIG_ENOCONV. */
+int gsyeig_refine(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t k, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, const float *U_lowprec, int64_t ldu, const gsyeig_opts *opts,
+                  const double *X0, int64_t ldx0, double *Lambda, double *X, int64_t ldx, gsyeig_info *info);
+
 /* BT1 (Eq. 4; Table 1): X = U^-1 Y in place for s column vectors (n x s
  * column-major, ldy >= n).  Asynchronous. */
 int gsyeig_backsolve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *U, int64_t ldu,
@@ -197,8 +275,15 @@ int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
                  const double *X, int64_t ldx, gsyeig_info *out);
 
 /* The whole path GS1 -> KI1..KI5 -> BT1 -> check (Eq. 1-4).
- * B is overwritten by U in its upper triangle (Section 2.1: the factor
- * overwrites B); its strict lower triangle is preserved.  Lambda (device, s)
+ * FP64 mode: B is overwritten by U in its upper triangle (Section 2.1: the
+ * factor overwrites B); its strict lower triangle is preserved.
+ * Mixed mode (opts->prec = GSYEIG_MIXED): B is not modified; GS1 runs with
+ * FP32 trailing updates into an internal FP32 factor U~, the Lanczos sweeps
+ * read FP32 copies of A and U~ (FP64 vectors, alpha/beta, re-orthogonal-
+ * isation and T), s + guard Ritz vectors are back-solved with U~ and
+ * refined as by gsyeig_refine; info reports both phases.  Returns
+ * GSYEIG_ENOCONV unless the FP32-sweep Lanczos met tol AND the refinement
+ * met eta_tol.  Lambda (device, s)
  * receives the eigenvalues ascending; X (device, n x s column-major,
  * ldx >= n) the B-orthonormal eigenvectors, each signed so that its entry
  * of largest magnitude (lowest index on ties) is positive.  *info (host,

@@ -29,6 +29,7 @@ EXPORTS = (
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
     "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_solve_batched",
+    "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
 )
 
 
@@ -52,7 +53,8 @@ class gsyeig_opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("block", ctypes.c_int), ("which", ctypes.c_int),
                 ("invert", ctypes.c_int), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("check_every", ctypes.c_int64), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
-                ("profile_every", ctypes.c_int64)]
+                ("profile_every", ctypes.c_int64), ("eta_tol", ctypes.c_double),
+                ("refine_iters", ctypes.c_int64), ("refine_inner", ctypes.c_int64), ("guard", ctypes.c_int64)]
 
 
 class gsyeig_info(ctypes.Structure):
@@ -60,7 +62,9 @@ class gsyeig_info(ctypes.Structure):
         (k, ctypes.c_double) for k in ("eta_max", "rho_f", "omega", "normA_f", "normB_f", "t_gs1_ms",
                                        "t_ki_ms", "t_ki5_ms", "t_bt1_ms", "t_check_ms", "t_total_ms")] + [
         ("prof_samples", ctypes.c_int64), ("t_ki1_ms_sum", ctypes.c_double),
-        ("t_ki2_ms_sum", ctypes.c_double), ("t_ki3_ms_sum", ctypes.c_double)]
+        ("t_ki2_ms_sum", ctypes.c_double), ("t_ki3_ms_sum", ctypes.c_double),
+        ("t_refine_ms", ctypes.c_double), ("eta_phase1", ctypes.c_double), ("refine_iters", ctypes.c_int64),
+        ("block_applies", ctypes.c_int64), ("block_cols", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +89,12 @@ def lib():
             "gsyeig_set_trsv_block": ([P, I64], I),
             "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
             "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
+            "gsyeig_trsv_lp": ([P, I64, P, I64, I, P, P], I),
+            "gsyeig_symv_lp": ([P, I64, P, I64, P, P], I),
+            "gsyeig_trsm_lp": ([P, I64, P, I64, I, I64, P, I64, P, I64], I),
+            "gsyeig_syev_small": ([P, I64, P, I64, I64, I, P, P, I64], I),
+            "gsyeig_refine": ([P, I64, I64, I64, P, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, I64, P, P,
+                               I64, ctypes.POINTER(gsyeig_info)], I),
             "gsyeig_trsv": ([P, I64, P, I64, I, P, P], I),
             "gsyeig_symv": ([P, I64, P, I64, P, P], I),
             "gsyeig_apply_op": ([P, I64, P, I64, P, I64, P, P], I),
@@ -184,6 +194,31 @@ def gsyeig_lanczos(ctx, n, s, A, lda, U, ldu, opts, theta, Y, ldy):
     rc = lib().gsyeig_lanczos(ctx, n, s, _p(A), lda, _p(U), ldu, ctypes.byref(opts) if opts else None,
                               _p(theta), _p(Y), ldy, ctypes.byref(steps))
     return rc, steps.value
+
+
+def gsyeig_trsv_lp(ctx, n, U, ldu, trans, b, x) -> int:
+    return lib().gsyeig_trsv_lp(ctx, n, _p(U), ldu, trans, _p(b), _p(x))
+
+
+def gsyeig_symv_lp(ctx, n, A, lda, x, y) -> int:
+    return lib().gsyeig_symv_lp(ctx, n, _p(A), lda, _p(x), _p(y))
+
+
+def gsyeig_trsm_lp(ctx, n, U, ldu, trans, k, V, ldv, X, ldx) -> int:
+    return lib().gsyeig_trsm_lp(ctx, n, _p(U), ldu, trans, k, _p(V), ldv, _p(X), ldx)
+
+
+def gsyeig_syev_small(ctx, N, H, ldh, nwant, which, w, Q, ldq) -> int:
+    return lib().gsyeig_syev_small(ctx, N, _p(H), ldh, nwant, which, _p(w), _p(Q), ldq)
+
+
+def gsyeig_refine(ctx, n, s, k, A, lda, B, ldb, U_lowprec, ldu, opts, X0, ldx0, Lambda, X, ldx):
+    """Returns (rc, info)."""
+    info = gsyeig_info()
+    rc = lib().gsyeig_refine(ctx, n, s, k, _p(A), lda, _p(B), ldb, _p(U_lowprec), ldu,
+                             ctypes.byref(opts) if opts else None, _p(X0), ldx0, _p(Lambda), _p(X), ldx,
+                             ctypes.byref(info))
+    return rc, info
 
 
 def gsyeig_backsolve(ctx, n, s, U, ldu, Y_to_X, ldy) -> int:

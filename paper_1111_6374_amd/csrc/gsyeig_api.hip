@@ -109,6 +109,17 @@ static void opts_fill_defaults(gsyeig_opts *o)
     o->seed = 6374;
     o->v0 = nullptr;
     o->profile_every = 0;
+    o->eta_tol = 1e-10;
+    o->refine_iters = 10;
+    o->refine_inner = 20;
+    o->guard = 0;
+}
+
+// width of the mixed-mode refinement block: s wanted + guard vectors
+static int64_t mixed_block(int64_t n, int64_t s, const gsyeig_opts *o)
+{
+    const int64_t g = (o->guard > 0) ? o->guard : std::max<int64_t>(8, cdiv(s, 4));
+    return std::min<int64_t>(n, std::min<int64_t>(s + g, syev_small_max() / 2));
 }
 
 static int64_t eff_max_steps(int64_t n, int64_t s, const gsyeig_opts *o)
@@ -180,19 +191,48 @@ static int prof_harvest(gsyeig_ctx *ctx)
     return 0;
 }
 
+// The implicit operator C = U^-T A U^-1 of KI1-KI3: FP64 A and U, or (mixed
+// mode) FP32 copies of both with FP64 super-block inverses.
+struct LzOp {
+    int f32;
+    const double *A; int64_t lda;
+    const double *U; int64_t ldu;
+    const double *Dinv;
+    const float *A32; int64_t lda32;
+    const float *U32; int64_t ldu32;
+    const double *sb;
+};
+
+static LzOp op_fp64(const double *A, int64_t lda, const double *U, int64_t ldu, const double *Dinv)
+{
+    LzOp op{};
+    op.A = A; op.lda = lda; op.U = U; op.ldu = ldu; op.Dinv = Dinv;
+    return op;
+}
+
 // KI1-KI3 into z (z may alias w); tmp is an n-vector of scratch.
-static int apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
-                    int64_t ldu, const double *Dinv, const double *w, double *z, double *tmp,
+static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w, double *z, double *tmp,
                     bool sample = false)
 {
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
-    TRY(solve_n(ctx, n, U, ldu, Dinv, w, tmp));
+    if (op.f32)
+        TRY(launch_trsv_sb_n_f32(op.U32, op.ldu32, n, op.sb, w, tmp, ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n,
+                                 ctx->stream));
+    else
+        TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
-    TRY(launch_symv(ctx, n, A, lda, tmp, z));
+    if (op.f32)
+        TRY(launch_symv_f32(ctx, n, op.A32, op.lda32, tmp, z));
+    else
+        TRY(launch_symv(ctx, n, op.A, op.lda, tmp, z));
     if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
-    TRY(solve_t(ctx, n, U, ldu, Dinv, z, z));
+    if (op.f32)
+        TRY(launch_trsv_sb_t_f32(op.U32, op.ldu32, n, op.sb, z, z, ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t,
+                                 ctx->stream));
+    else
+        TRY(solve_t(ctx, n, op.U, op.ldu, op.Dinv, z, z));
     if (sample) {
         HIP_TRY(hipEventRecord(e[3], ctx->stream));
         ctx->npev += 4;
@@ -222,13 +262,12 @@ static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
 }
 
 // One Lanczos step k (KI1-KI4): w_k = V[:, k] -> w_{k+1} = V[:, k+1].
-static int lz_step(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U,
-                   int64_t ldu, const double *Dinv, double *V, int64_t ldv, double *alpha,
+static int lz_step(gsyeig_ctx *ctx, int64_t n, const LzOp &op, double *V, int64_t ldv, double *alpha,
                    double *beta, int64_t k, const LzBufs &b, bool sample = false)
 {
     const double *wk = V + k * ldv;
     const double *wp = (k > 0) ? V + (k - 1) * ldv : wk;
-    TRY(apply_op(ctx, n, A, lda, U, ldu, Dinv, wk, b.z, b.tmp, sample));
+    TRY(apply_op(ctx, n, op, wk, b.z, b.tmp, sample));
     TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream));
     TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream));
     TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream));
@@ -236,26 +275,29 @@ static int lz_step(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, con
     return 0;
 }
 
-// KI1-KI5 with convergence checks; Ritz values -> theta (s), vectors -> Y.
+// KI1-KI5 with convergence checks.  The nvec >= s extreme Ritz pairs are
+// extracted (ascending; values -> theta_out, vectors -> Y); the run stops
+// when the s wanted ones among them (the first s for which = 0, the last s
+// for which = 1) meet tol.
 struct LzResult {
     int64_t steps;
     int64_t nconv;
     float t_loop_ms, t_ritz_ms;
 };
 
-static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
-                    const double *U, int64_t ldu, const double *Dinv, const gsyeig_opts *o,
-                    double *theta_out, double *Y, int64_t ldy, LzResult *res)
+static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const LzOp &op,
+                    const gsyeig_opts *o, double *theta_out, double *Y, int64_t ldy, LzResult *res)
 {
-    const int64_t mmax = eff_max_steps(n, s, o);
+    const int64_t mmax = std::max<int64_t>(eff_max_steps(n, s, o), std::min<int64_t>(nvec, n));
+    const int64_t w0 = o->which ? nvec - s : 0;
     const int64_t ldv = round_ld(n);
     void *p;
     TRY(ws_get(ctx, WS_V, sizeof(double) * (size_t)ldv * (size_t)(mmax + 1), &p));
     double *V = (double *)p;
-    // T: alpha (mmax), beta (mmax), theta (s+1), lastcomp (s)
-    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * s + 16), &p));
-    double *alpha = (double *)p, *beta = alpha + mmax, *theta = beta + mmax, *lastc = theta + s + 1;
-    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)s * 7 * (size_t)mmax, &p));
+    // T: alpha (mmax), beta (mmax), theta (nvec+1), lastcomp (nvec)
+    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * nvec + 16), &p));
+    double *alpha = (double *)p, *beta = alpha + mmax, *theta = beta + mmax, *lastc = theta + nvec + 1;
+    TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)nvec * 7 * (size_t)mmax, &p));
     double *tri = (double *)p;
     LzBufs b;
     TRY(lz_bufs(ctx, n, mmax, &b));
@@ -280,13 +322,13 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int6
     const int64_t pe = o->profile_every;
     for (int64_t k = 0; k < mmax; ++k) {
         const bool sample = pe > 0 && (k % pe) == pe - 1;
-        TRY(lz_step(ctx, n, A, lda, U, ldu, Dinv, V, ldv, alpha, beta, k, b, sample));
+        TRY(lz_step(ctx, n, op, V, ldv, alpha, beta, k, b, sample));
         m = k + 1;
         checked_at_m = false;
-        if (m >= s && (m % every == 0 || m == mmax)) {
-            TRY(launch_tri_bisect(alpha, beta, m, s, o->which, theta, ctx->stream));
-            TRY(launch_tri_vectors(alpha, beta, m, s, theta, nullptr, 0, tri, 0, lastc, ctx->stream));
-            TRY(launch_conv_count(theta, lastc, beta + (m - 1), s, o->tol, nconv_d, ctx->stream));
+        if (m >= nvec && (m % every == 0 || m == mmax)) {
+            TRY(launch_tri_bisect(alpha, beta, m, nvec, o->which, theta, ctx->stream));
+            TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, nullptr, 0, tri, 0, lastc, ctx->stream));
+            TRY(launch_conv_count(theta, lastc, beta + (m - 1), nvec, w0, s, o->tol, nconv_d, ctx->stream));
             HIP_TRY(hipMemcpyAsync(nconv_h, nconv_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));
             TRY(prof_harvest(ctx));
@@ -296,21 +338,21 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int6
         }
     }
     if (!checked_at_m) {
-        TRY(launch_tri_bisect(alpha, beta, m, s, o->which, theta, ctx->stream));
+        TRY(launch_tri_bisect(alpha, beta, m, nvec, o->which, theta, ctx->stream));
     }
     HIP_TRY(hipEventRecord(ctx->ev[7], ctx->stream));
-    // Ritz vectors: S (m x s) by inverse iteration, Y = V_m S
-    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)s, &p));
+    // Ritz vectors: S (m x nvec) by inverse iteration, Y = V_m S
+    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)nvec, &p));
     double *S = (double *)p;
-    TRY(launch_tri_vectors(alpha, beta, m, s, theta, S, m, tri, 1, lastc, ctx->stream));
+    TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
     GemmDesc d{};
-    d.m = n; d.n = s; d.k = m;
+    d.m = n; d.n = nvec; d.k = m;
     d.A = V; d.lda = ldv; d.a_layout = 0;
     d.B = S; d.ldb = m; d.b_layout = 0;
     d.C = Y; d.ldc = ldy; d.c_layout = 0;
     d.alpha = 1.0; d.beta = 0.0;
     TRY(launch_gemm_f64(d, ctx->stream));
-    TRY(launch_copy(theta, theta_out, s, ctx->stream));
+    TRY(launch_copy(theta, theta_out, nvec, ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     TRY(prof_harvest(ctx));
@@ -360,6 +402,45 @@ static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, dou
     return prepare_solves(ctx, n, B, ldb, Dinv);
 }
 
+// GS1 in mixed precision: W = fl32(upper(B)) (B untouched), 64x64 diagonal
+// blocks factored in FP64, panel and trailing SYRK as FP32 MFMA products
+// with FP32 accumulation on the FP32 matrix; U~ (FP32) is left in W's upper
+// triangle with zeros below.  Dinv then holds the FP64 inverses of the
+// stored FP32 diagonal blocks.
+static int potrf_mixed_enqueue(gsyeig_ctx *ctx, int64_t n, const double *B, int64_t ldb, float *W,
+                               int64_t ldw, double *Dinv, int *info_d)
+{
+    HIP_TRY(hipMemsetAsync(info_d, 0, sizeof(int), ctx->stream));
+    TRY(launch_upper_to_f32(B, ldb, W, ldw, n, ctx->stream));
+    const int64_t nblk = cdiv(n, NB);
+    for (int64_t kb = 0; kb < nblk; ++kb) {
+        TRY(launch_potrf_diag_f32(W, ldw, n, kb, Dinv, info_d, ctx->stream));
+        const int64_t r0 = kb * NB;
+        const int64_t r = std::min<int64_t>(NB, n - r0);
+        const int64_t c0 = r0 + r;
+        const int64_t m2 = n - c0;
+        if (m2 <= 0) break;
+        GemmDesc pd{};
+        pd.m = r; pd.n = m2; pd.k = r;
+        pd.A = Dinv + kb * NB * NB; pd.lda = NB; pd.a_layout = 0;
+        pd.B = W + r0 * ldw + c0; pd.ldb = ldw; pd.b_layout = 1; pd.b_f32 = 1;
+        pd.C = W + r0 * ldw + c0; pd.ldc = ldw; pd.c_layout = 1; pd.c_f32 = 1;
+        pd.alpha = 1.0; pd.beta = 0.0;
+        pd.f32 = 1;
+        TRY(launch_gemm(pd, ctx->stream));
+        GemmDesc sd{};
+        sd.m = m2; sd.n = m2; sd.k = r;
+        sd.A = W + r0 * ldw + c0; sd.lda = ldw; sd.a_layout = 0; sd.a_f32 = 1;
+        sd.B = W + r0 * ldw + c0; sd.ldb = ldw; sd.b_layout = 1; sd.b_f32 = 1;
+        sd.C = W + c0 * ldw + c0; sd.ldc = ldw; sd.c_layout = 1; sd.c_f32 = 1;
+        sd.alpha = -1.0; sd.beta = 1.0;
+        sd.upper_only = 1;
+        sd.f32 = 1;
+        TRY(launch_gemm(sd, ctx->stream));
+    }
+    return launch_diag_inv_f32(W, ldw, n, Dinv, ctx->stream);
+}
+
 static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
                          const double *B, int64_t ldb, const double *Bdiag, const double *Lambda,
                          const double *X, int64_t ldx, double *res_d)
@@ -395,6 +476,109 @@ static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A,
     TRY(launch_fro_norm_parts(B, ldb, n, Bdiag ? 2 : 0, Bdiag, partB, ctx->stream));
     TRY(launch_check_finalize(cols, s, G, s, partA, PA, partB, PA, Lambda, res_d, ctx->stream));
     return 0;
+}
+
+// FP32 operator data for a factor U~ (FP32): A~ = fl32(A), the FP64 inverses
+// of U~'s diagonal blocks and its super-block inverses.
+static int mixed_operator(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const float *U32,
+                          int64_t ldu32, bool have_dinv, LzOp *op)
+{
+    const int64_t ld32 = round_ld(n);
+    void *p;
+    TRY(ws_get(ctx, WS_A32, sizeof(float) * (size_t)ld32 * (size_t)n, &p));
+    float *A32 = (float *)p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    double *sb = (double *)p;
+    TRY(launch_to_f32(A, lda, A32, ld32, n, n, ctx->stream));
+    if (!have_dinv) TRY(launch_diag_inv_f32(U32, ldu32, n, Dinv, ctx->stream));
+    TRY(launch_make_sb_f32(U32, ldu32, n, Dinv, sb, ctx->stream));
+    *op = LzOp{};
+    op->f32 = 1;
+    op->Dinv = Dinv;
+    op->A32 = A32; op->lda32 = ld32;
+    op->U32 = U32; op->ldu32 = ldu32;
+    op->sb = sb;
+    return 0;
+}
+
+// Mixed mode of gsyeig_solve: GS1 with FP32 trailing updates, Lanczos with
+// FP32 sweeps (FP64 vectors, alpha/beta, CGS2, T), Ritz vectors for s +
+// guard pairs, X0 = U~^-1 Y, FP64 refinement on (A, B), FP64 check.  B is
+// not modified.
+static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, const gsyeig_opts &o, double *Lambda, double *X, int64_t ldx,
+                       gsyeig_info *info)
+{
+    const int64_t k = mixed_block(n, s, &o);
+    if (k < s) return -3;
+    const int64_t ld32 = round_ld(n);
+    void *p;
+    TRY(ws_get(ctx, WS_U32, sizeof(float) * (size_t)ld32 * (size_t)n, &p));
+    float *U32 = (float *)p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    int *info_d = (int *)ctx->dscal + 16;
+    gsyeig_info inf;
+    memset(&inf, 0, sizeof(inf));
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    TRY(potrf_mixed_enqueue(ctx, n, B, ldb, U32, ld32, Dinv, info_d));
+    LzOp op;
+    TRY(mixed_operator(ctx, n, A, lda, U32, ld32, true, &op));
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+    int *hi = (int *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(hi, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (hi[0] != 0) return hi[0];
+
+    double *Y;
+    int64_t ldy;
+    TRY(refine_x0(ctx, n, k, &Y, &ldy));
+    TRY(ws_get(ctx, WS_BDIAG, sizeof(double) * (size_t)(n + 8), &p));
+    double *theta_k = (double *)p;
+    LzResult r{};
+    TRY(lz_solve(ctx, n, s, k, op, &o, theta_k, Y, ldy, &r));
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    TRY(launch_backsolve_f32(U32, ld32, n, k, Dinv, Y, ldy, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
+    RefineOp rop{U32, ld32, op.sb, op.A32, ld32};
+    RefineCfg cfg{o.eta_tol, o.refine_iters, o.refine_inner};
+    RefineStats rs{};
+    TRY(refine_run(ctx, n, s, k, o.which, A, lda, B, ldb, rop, cfg, Lambda, X, ldx, &rs));
+    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
+    double *res_d = (double *)ctx->dscal + 64;
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, nullptr, Lambda, X, ldx, res_d));
+    HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
+    double *h = (double *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    inf.eta_max = h[0];
+    inf.rho_f = h[1];
+    inf.omega = h[2];
+    inf.normA_f = h[3];
+    inf.normB_f = h[4];
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
+    inf.t_ki_ms = r.t_loop_ms;
+    inf.t_ki5_ms = r.t_ritz_ms;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_refine_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5])); inf.t_check_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[5])); inf.t_total_ms = t;
+    inf.steps = r.steps;
+    inf.converged = (r.nconv >= s) ? rs.nconv : std::min<int64_t>(r.nconv, rs.nconv);
+    inf.prof_samples = ctx->prof_samples;
+    inf.t_ki1_ms_sum = ctx->prof_ms[0];
+    inf.t_ki2_ms_sum = ctx->prof_ms[1];
+    inf.t_ki3_ms_sum = ctx->prof_ms[2];
+    inf.eta_phase1 = rs.eta0;
+    inf.refine_iters = rs.iters;
+    inf.block_applies = rs.block_applies;
+    inf.block_cols = rs.kept;
+    if (info) *info = inf;
+    return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -484,6 +668,12 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     b += trsv_sb_bytes(n);                                        // super-block solve data
     b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
     b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
+    if (o.prec == GSYEIG_MIXED) {
+        const int64_t k = mixed_block(n, s, &o);
+        b += 2 * sizeof(float) * (size_t)ldv * (size_t)n;           // A~, U~ (FP32)
+        b += refine_bytes(n, k);                                      // refinement blocks
+        b += sizeof(double) * (size_t)(k - s) * 8 * (size_t)mmax;     // wider Ritz extraction
+    }
     *bytes = b;
     return 0;
 }
@@ -496,10 +686,16 @@ int gsyeig_potrf(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, const gsyei
     if (n < 1) return -2;
     if (!B) return -3;
     if (ldb < n) return -4;
-    if (U_lowprec) return -6;
+    if (opts && opts->prec == GSYEIG_MIXED && !U_lowprec) return -6;
     double *Dinv;
     int *info_d = (int *)ctx->dscal + 16;
-    TRY(potrf_enqueue(ctx, n, B, ldb, &Dinv, info_d));
+    if (U_lowprec) {
+        void *p;
+        TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+        TRY(potrf_mixed_enqueue(ctx, n, B, ldb, (float *)U_lowprec, n, (double *)p, info_d));
+    } else {
+        TRY(potrf_enqueue(ctx, n, B, ldb, &Dinv, info_d));
+    }
     int *h = (int *)ctx->host_pinned;
     HIP_TRY(hipMemcpyAsync(h, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -549,7 +745,7 @@ int gsyeig_apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, co
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
     void *p;
     TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
-    return apply_op(ctx, n, A, lda, U, ldu, Dinv, w, z, (double *)p);
+    return apply_op(ctx, n, op_fp64(A, lda, U, ldu, Dinv), w, z, (double *)p);
 }
 
 int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, int64_t lda,
@@ -574,7 +770,8 @@ int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, i
     LzBufs b;
     TRY(lz_bufs(ctx, n, k, &b));
     TRY(launch_normalize_into(v0, V, n, b.red, nullptr, ctx->stream));
-    for (int64_t j = 0; j < k; ++j) TRY(lz_step(ctx, n, A, lda, U, ldu, Dinv, V, ldv, alpha, beta, j, b));
+    const LzOp op = op_fp64(A, lda, U, ldu, Dinv);
+    for (int64_t j = 0; j < k; ++j) TRY(lz_step(ctx, n, op, V, ldv, alpha, beta, j, b));
     return 0;
 }
 
@@ -620,7 +817,7 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
     double *Dinv;
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
     LzResult r{};
-    TRY(lz_solve(ctx, n, s, A, lda, U, ldu, Dinv, &o, theta, Y, ldy, &r));
+    TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, U, ldu, Dinv), &o, theta, Y, ldy, &r));
     if (steps_out) *steps_out = r.steps;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
 }
@@ -681,11 +878,13 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (ldb < n) return -7;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
-    if (o.prec != GSYEIG_FP64 || o.block != 1 || o.invert || (o.which != 0 && o.which != 1))
+    if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block != 1 || o.invert ||
+        (o.which != 0 && o.which != 1))
         return -8;
     if (!Lambda) return -9;
     if (!X) return -10;
     if (ldx < n) return -11;
+    if (o.prec == GSYEIG_MIXED) return solve_mixed(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
 
     gsyeig_info inf;
     memset(&inf, 0, sizeof(inf));
@@ -704,7 +903,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (hi[0] != 0) return hi[0];
 
     LzResult r{};
-    TRY(lz_solve(ctx, n, s, A, lda, B, ldb, Dinv, &o, Lambda, X, ldx, &r));
+    TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r));
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
     TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
@@ -735,6 +934,146 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.t_ki3_ms_sum = ctx->prof_ms[2];
     if (info) *info = inf;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+}
+
+int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int trans, const double *b,
+                   double *x)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!U) return -3;
+    if (ldu < n) return -4;
+    if (trans != 0 && trans != 1) return -5;
+    if (!b) return -6;
+    if (!x) return -7;
+    TRY(ctl_reserve(ctx, n));
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    double *sb = (double *)p;
+    TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
+    TRY(launch_make_sb_f32(U, ldu, n, Dinv, sb, ctx->stream));
+    if (trans == 0)
+        TRY(launch_trsv_sb_n_f32(U, ldu, n, sb, b, x, ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n, ctx->stream));
+    else
+        TRY(launch_trsv_sb_t_f32(U, ldu, n, sb, b, x, ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t, ctx->stream));
+    return ctl_check(ctx);
+}
+
+int gsyeig_symv_lp(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double *y)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!x) return -5;
+    if (!y) return -6;
+    TRY(launch_symv_f32(ctx, n, A, lda, x, y));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int gsyeig_trsm_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int trans, int64_t k,
+                   const double *V, int64_t ldv, double *X, int64_t ldx)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!U) return -3;
+    if (ldu < n) return -4;
+    if (trans != 0 && trans != 1) return -5;
+    if (k < 1) return -6;
+    if (!V) return -7;
+    if (ldv < n) return -8;
+    if (!X) return -9;
+    if (ldx < n) return -10;
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    double *sb = (double *)p;
+    const int64_t ldw = round_ld(n);
+    TRY(ws_get(ctx, WS_Y, sizeof(double) * (size_t)ldw * (size_t)k, &p));
+    double *W = (double *)p;
+    TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
+    TRY(launch_make_sb_f32(U, ldu, n, Dinv, sb, ctx->stream));
+    TRY(launch_blk_copy(V, ldv, W, ldw, n, k, ctx->stream));
+    TRY(launch_trsm_sb_f32(trans, U, ldu, n, sb, W, ldw, X, ldx, k, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int gsyeig_syev_small(gsyeig_ctx *ctx, int64_t N, const double *H, int64_t ldh, int64_t nwant, int which,
+                      double *w, double *Q, int64_t ldq)
+{
+    if (!ctx) return -1;
+    if (N < 1 || N > syev_small_max()) return -2;
+    if (!H) return -3;
+    if (ldh < N) return -4;
+    if (nwant < 1 || nwant > N) return -5;
+    if (which != 0 && which != 1) return -6;
+    if (!w) return -7;
+    if (!Q) return -8;
+    if (ldq < N) return -9;
+    void *p;
+    const size_t need = sizeof(double) * (size_t)(N * N + N * nwant + nwant + 8) + syev_small_scratch(N, nwant);
+    TRY(ws_get(ctx, WS_S, need, &p));
+    double *Hc = (double *)p, *Qc = Hc + N * N, *wc = Qc + N * nwant, *scr = wc + nwant + 8;
+    TRY(launch_blk_copy(H, ldh, Hc, N, N, N, ctx->stream));
+    TRY(syev_small(N, Hc, nwant, which, wc, Qc, scr, ctx->stream));
+    TRY(launch_copy(wc, w, nwant, ctx->stream));
+    TRY(launch_blk_copy(Qc, N, Q, ldq, N, nwant, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int gsyeig_refine(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t k, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, const float *U_lowprec, int64_t ldu, const gsyeig_opts *opts,
+                  const double *X0, int64_t ldx0, double *Lambda, double *X, int64_t ldx, gsyeig_info *info)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (s < 1 || s > n) return -3;
+    if (k < s || k > n || 2 * k > syev_small_max()) return -4;
+    if (!A || lda < n) return -5;
+    if (!B || ldb < n) return -7;
+    if (!U_lowprec || ldu < n) return -9;
+    gsyeig_opts o;
+    if (opts) o = *opts; else opts_fill_defaults(&o);
+    if (o.which != 0 && o.which != 1) return -11;
+    if (!X0 || ldx0 < n) return -12;
+    if (!Lambda) return -14;
+    if (!X || ldx < n) return -15;
+    LzOp op;
+    TRY(mixed_operator(ctx, n, A, lda, U_lowprec, ldu, false, &op));
+    double *Z0;
+    int64_t ldz;
+    TRY(refine_x0(ctx, n, k, &Z0, &ldz));
+    TRY(launch_blk_copy(X0, ldx0, Z0, ldz, n, k, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    RefineOp rop{U_lowprec, ldu, op.sb, op.A32, op.lda32};
+    RefineCfg cfg{o.eta_tol, o.refine_iters, o.refine_inner};
+    RefineStats rs{};
+    TRY(refine_run(ctx, n, s, k, o.which, A, lda, B, ldb, rop, cfg, Lambda, X, ldx, &rs));
+    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (info) {
+        gsyeig_info inf;
+        memset(&inf, 0, sizeof(inf));
+        float t;
+        HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+        inf.t_refine_ms = t;
+        inf.t_total_ms = t;
+        inf.eta_max = rs.eta;
+        inf.eta_phase1 = rs.eta0;
+        inf.converged = rs.nconv;
+        inf.refine_iters = rs.iters;
+        inf.block_applies = rs.block_applies;
+        inf.block_cols = rs.kept;
+        *info = inf;
+    }
+    return (rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
 }
 
 // Many independent pencils (row a10 of the hot path): instances are taken

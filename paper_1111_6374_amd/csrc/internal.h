@@ -55,6 +55,9 @@ enum WsSlot {
     WS_BDIAG,      // saved diagonal of B
     WS_SYMVMAP,    // SYMV work list
     WS_SB,         // super-block solve data: Uinv, Uinv^T, N, N' (SB x SB per super-block)
+    WS_A32,        // FP32 copy of A (mixed mode)
+    WS_U32,        // FP32 Cholesky factor (mixed mode)
+    WS_REFINE,     // blocks and small matrices of the FP64 refinement
     WS_COUNT
 };
 
@@ -98,14 +101,20 @@ int ctl_reserve(gsyeig_ctx *ctx, int64_t rows);
 // strict LOWER triangle of a row-major matrix with diagonal from `diag`.
 struct GemmDesc {
     int64_t m, n, k;
-    const double *A; int64_t lda; int a_layout;
-    const double *B; int64_t ldb; int b_layout;
-    double *C; int64_t ldc; int c_layout;
+    const void *A; int64_t lda; int a_layout;
+    const void *B; int64_t ldb; int b_layout;
+    void *C; int64_t ldc; int c_layout;
     double alpha, beta;
     const double *a_diag;  // for a_layout == 2
     int upper_only;        // write only C(i, j) with i <= j (logical indices)
+    int a_f32, b_f32, c_f32;  // storage of A / B / C is FP32 (else FP64)
+    int f32;                  // FP32 compute (MFMA f32, FP32 accumulation); else FP64
+    int splitk;               // > 1: split K into chunks summed through `part`
+    double *part;             // split-K scratch: gemm_splitk_parts(d) * m * n doubles
 };
+int launch_gemm(const GemmDesc &d, hipStream_t st);
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
+int64_t gemm_splitk_parts(const GemmDesc &d);
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
 // super-block solves (k_trsv_sb.hip); sb = [Uinv | Uinv^T | N | N']
@@ -117,6 +126,24 @@ int launch_trsv_sb_n(const double *U, int64_t ldu, int64_t n, const double *sb, 
                      double *x, double *rstage, PCtl *ctl, hipStream_t st);
 int launch_trsv_sb_t(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
                      double *x, double *rstage, PCtl *ctl, hipStream_t st);
+// FP32-storage variants (mixed mode) and the FP64 -> FP32 copy
+// (U stored FP32, super-block data FP64)
+int launch_trsv_sb_n_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                         double *x, double *rstage, PCtl *ctl, hipStream_t st);
+int launch_trsv_sb_t_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                         double *x, double *rstage, PCtl *ctl, hipStream_t st);
+int launch_make_sb_f32(const float *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
+                       hipStream_t st);
+int launch_potrf_diag_f32(float *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,
+                          hipStream_t st);
+int launch_diag_inv_f32(const float *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
+int launch_backsolve_f32(const float *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv,
+                         double *Y, int64_t ldy, hipStream_t st);
+int launch_upper_to_f32(const double *B, int64_t ldb, float *W, int64_t ldw, int64_t n, hipStream_t st);
+int launch_symv_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x,
+                    double *y);
+int launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
+                  hipStream_t st);
 // M holds [M_i | M'_i] for all blocks (see launch_make_m)
 int launch_make_m(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *M,
                   hipStream_t st);
@@ -154,7 +181,36 @@ int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64
                        const double *theta, double *S, int64_t lds, double *scratch, int clustered,
                        double *lastcomp, hipStream_t st);
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
-                      int64_t nwant, double tol, int *nconv, hipStream_t st);
+                      int64_t nwant, int64_t i0, int64_t cnt, double tol, int *nconv, hipStream_t st);
+
+// mixed-precision refinement (k_refine.hip)
+struct RefineOp {          // the FP32 operator C~ = U~^-T A~ U~^-1
+    const float *U32; int64_t ldu32;
+    const double *sb;      // super-block inverses of U~ (FP64)
+    const float *A32; int64_t lda32;
+};
+struct RefineCfg {
+    double eta_tol;        // stop when max eta over the wanted pairs <= eta_tol
+    int64_t max_iters;     // correction rounds
+    int64_t inner;         // MINRES steps per round
+};
+struct RefineStats {
+    int64_t iters, block_applies, kept, nconv;
+    double eta0, eta;
+};
+size_t refine_bytes(int64_t n, int64_t k);
+int refine_x0(gsyeig_ctx *ctx, int64_t n, int64_t k, double **X0, int64_t *ld);
+int refine_run(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t k, int which, const double *A, int64_t lda,
+               const double *B, int64_t ldb, const RefineOp &op, const RefineCfg &cfg, double *Lambda,
+               double *X, int64_t ldx, RefineStats *out);
+int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const double *sb, double *V,
+                       int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st);
+int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
+                    hipStream_t st);
+size_t syev_small_scratch(int64_t N, int64_t nwant);
+int syev_small(int64_t N, double *H, int64_t nwant, int which, double *w, double *Q, double *scratch,
+               hipStream_t st);
+int64_t syev_small_max();
 
 // accuracy check
 int fro_parts(int64_t n);

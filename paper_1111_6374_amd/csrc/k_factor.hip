@@ -12,7 +12,8 @@ namespace {
 // writes Dinv_kk = U_kk^-1 (64 x 64 row-major, zero outside the block).
 // A non-positive pivot records the global 1-based index in *info (first
 // failure wins) and is replaced by 1 so the sweep continues without NaNs.
-__global__ __launch_bounds__(256) void k_potrf_diag(double *B, int64_t ldb, int64_t n, int64_t kb,
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_diag(T *B, int64_t ldb, int64_t n, int64_t kb,
                                                     double *Dinv, int *info)
 {
     __shared__ double a[NB][NB + 1];
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *B, int64_t ldb, int6
     const int r = (int)((n - r0) < NB ? (n - r0) : NB);
     for (int t = tid; t < NB * NB; t += 256) {
         const int i = t / NB, j = t % NB;
-        a[i][j] = (i < r && j < r && j >= i) ? B[(r0 + i) * ldb + r0 + j] : 0.0;
+        a[i][j] = (i < r && j < r && j >= i) ? (double)B[(r0 + i) * ldb + r0 + j] : 0.0;
         x[i][j] = 0.0;
     }
     __syncthreads();
@@ -60,14 +61,14 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *B, int64_t ldb, int6
     __syncthreads();
     for (int t = tid; t < NB * NB; t += 256) {
         const int i = t / NB, j = t % NB;
-        if (i < r && j < r && j >= i) B[(r0 + i) * ldb + r0 + j] = a[i][j];
+        if (i < r && j < r && j >= i) B[(r0 + i) * ldb + r0 + j] = (T)a[i][j];
         Dinv[kb * NB * NB + t] = (i < r && j < r) ? x[i][j] : 0.0;
     }
 }
 
 // Dinv_I = U_II^-1 for every diagonal block of an existing factor U.
-__global__ __launch_bounds__(256) void k_diag_inv(const double *U, int64_t ldu, int64_t n,
-                                                  double *Dinv)
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_inv(const T *U, int64_t ldu, int64_t n, double *Dinv)
 {
     __shared__ double a[NB][NB + 1];
     __shared__ double x[NB][NB + 1];
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const double *U, int64_t ldu, 
     const int r = (int)((n - r0) < NB ? (n - r0) : NB);
     for (int t = tid; t < NB * NB; t += 256) {
         const int i = t / NB, j = t % NB;
-        a[i][j] = (i < r && j < r && j >= i) ? U[(r0 + i) * ldu + r0 + j] : 0.0;
+        a[i][j] = (i < r && j < r && j >= i) ? (double)U[(r0 + i) * ldu + r0 + j] : 0.0;
         x[i][j] = 0.0;
     }
     __syncthreads();
@@ -154,18 +155,51 @@ __global__ __launch_bounds__(256) void k_sign_normalise(double *X, int64_t ldx, 
         for (int64_t i = tid; i < n; i += 256) x[i] = -x[i];
 }
 
+// W = fl32(upper triangle of B), zero below the diagonal; row r per blockIdx.y
+__global__ void k_upper_to_f32(const double *__restrict__ B, int64_t ldb, float *__restrict__ W,
+                               int64_t ldw, int64_t n, int64_t r0)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = r0 + blockIdx.y;
+    if (c < n && r < n) W[r * ldw + c] = (c >= r) ? (float)B[r * ldb + c] : 0.0f;
+}
+
 }  // namespace
+
+int launch_upper_to_f32(const double *B, int64_t ldb, float *W, int64_t ldw, int64_t n, hipStream_t st)
+{
+    for (int64_t r0 = 0; r0 < n; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, n - r0);
+        hipLaunchKernelGGL(k_upper_to_f32, dim3((unsigned)cdiv(n, 256), (unsigned)nr), dim3(256), 0, st, B,
+                           ldb, W, ldw, n, r0);
+        if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    }
+    return 0;
+}
 
 int launch_potrf_diag(double *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, B, ldb, n, kb, Dinv, info);
+    hipLaunchKernelGGL(k_potrf_diag<double>, dim3(1), dim3(256), 0, st, B, ldb, n, kb, Dinv, info);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+int launch_potrf_diag_f32(float *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_potrf_diag<float>, dim3(1), dim3(256), 0, st, B, ldb, n, kb, Dinv, info);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)cdiv(n, NB)), dim3(256), 0, st, U, ldu, n, Dinv);
+    hipLaunchKernelGGL(k_diag_inv<double>, dim3((unsigned)cdiv(n, NB)), dim3(256), 0, st, U, ldu, n, Dinv);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+int launch_diag_inv_f32(const float *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_inv<float>, dim3((unsigned)cdiv(n, NB)), dim3(256), 0, st, U, ldu, n, Dinv);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
@@ -176,9 +210,11 @@ int launch_copy_diag(const double *B, int64_t ldb, int64_t n, double *d, hipStre
 }
 
 // X = U^-1 Y by block back-substitution from the last block row up:
-//   X_kb = Dinv_kb Y_kb;   Y_{0:kb} -= U_{0:kb, kb} X_kb  (MFMA update).
-int launch_backsolve(const double *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv,
-                     double *Y, int64_t ldy, hipStream_t st)
+//   X_kb = Dinv_kb Y_kb;   Y_{0:kb} -= U_{0:kb, kb} X_kb  (MFMA update, FP64).
+// U may be stored FP64 or FP32; right-hand sides and arithmetic are FP64.
+template <typename T>
+static int backsolve_t(const T *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv, double *Y,
+                       int64_t ldy, hipStream_t st)
 {
     const int64_t nblk = cdiv(n, NB);
     for (int64_t kb = nblk - 1; kb >= 0; --kb) {
@@ -191,12 +227,25 @@ int launch_backsolve(const double *U, int64_t ldu, int64_t n, int64_t s, const d
         GemmDesc d{};
         d.m = r0; d.n = s; d.k = r;
         d.A = U + r0; d.lda = ldu; d.a_layout = 1;          // A(i,k) = U[i, r0 + k]
+        d.a_f32 = sizeof(T) == 4;
         d.B = Y + r0; d.ldb = ldy; d.b_layout = 0;          // B(k,j) = X[r0 + k, j]
         d.C = Y; d.ldc = ldy; d.c_layout = 0;
         d.alpha = -1.0; d.beta = 1.0;
-        if (launch_gemm_f64(d, st)) return GSYEIG_EHIP;
+        if (launch_gemm(d, st)) return GSYEIG_EHIP;
     }
     return 0;
+}
+
+int launch_backsolve(const double *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv,
+                     double *Y, int64_t ldy, hipStream_t st)
+{
+    return backsolve_t<double>(U, ldu, n, s, Dinv, Y, ldy, st);
+}
+
+int launch_backsolve_f32(const float *U, int64_t ldu, int64_t n, int64_t s, const double *Dinv,
+                         double *Y, int64_t ldy, hipStream_t st)
+{
+    return backsolve_t<float>(U, ldu, n, s, Dinv, Y, ldy, st);
 }
 
 int launch_sign_normalise(double *X, int64_t ldx, int64_t n, int64_t s, hipStream_t st)

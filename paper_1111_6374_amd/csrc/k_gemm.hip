@@ -1,62 +1,89 @@
-// k_gemm.hip -- FP64 dense tile contraction on CDNA4 matrix cores.
+// k_gemm.hip -- dense tile contraction on CDNA4 matrix cores, FP64 or FP32.
 //
 // C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j) over logical indices,
 // with each operand's storage chosen by a layout code (column-major,
-// row-major, or symmetric-from-lower-triangle).  Used where the path is a
-// dense contraction: the Cholesky panel and trailing SYRK update (Eq. 2),
-// the Ritz vectors Y = V_m S (key KI5), the block back-substitution update
-// (Eq. 4) and the FP64 residual check.
+// row-major, or symmetric-from-lower-triangle) and a storage type (FP64 or
+// FP32; values are converted to the compute type as they are loaded).  Used
+// where the path is a dense contraction: the Cholesky panel and trailing
+// SYRK update (Eq. 2), the Ritz vectors Y = V_m S (key KI5), the block
+// back-substitution (Eq. 4), the block operator of the mixed-precision
+// refinement and the FP64 residual check.
+//
+// Compute types: FP64 on v_mfma_f64_16x16x4_f64, FP32 on
+// v_mfma_f32_16x16x4_f32 with FP32 accumulation (the mixed-precision
+// trailing updates and block sweeps).
 //
 // Tiling: one 256-thread workgroup owns a 64x64 tile of C; its four wave64s
-// each own a 32x32 quadrant = 2x2 blocks of v_mfma_f64_16x16x4_f64.  K is
-// staged through LDS 16 at a time, the next slab prefetched into registers
-// while the current one is multiplied.
+// each own a 32x32 quadrant = 2x2 MFMA blocks of 16x16.  K is staged through
+// LDS 16 at a time, the next slab prefetched into registers while the
+// current one is multiplied.  With split-K, blockIdx.z owns one K chunk and
+// writes its partial tile to scratch; a second kernel adds the chunks in a
+// fixed order (reproducible) and applies alpha/beta.
 #include "internal.h"
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
 constexpr int TM = 64, TN = 64, TK = 16;
-constexpr int LDS_PAD = 2;  // keeps the 16-wide operand reads on distinct banks
 
-template <int L>
-__device__ __forceinline__ double load_op(const double *p, int64_t ld, int64_t i, int64_t j,
-                                          const double *diag)
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = dbl4; static constexpr int pad = 2; };
+template <> struct Acc<float> { using type = flt4; static constexpr int pad = 16; };
+
+template <typename TS, int L>
+__device__ __forceinline__ TS load_op(const TS *p, int64_t ld, int64_t i, int64_t j, const double *diag)
 {
     if constexpr (L == 0) return p[j * ld + i];
     else if constexpr (L == 1) return p[i * ld + j];
     else {
-        if (i == j) return diag[i];
+        if (i == j) return (TS)diag[i];
         return (i > j) ? p[i * ld + j] : p[j * ld + i];
     }
 }
 
 struct Args {
     int64_t m, n, k;
-    const double *A; int64_t lda;
-    const double *B; int64_t ldb;
-    double *C; int64_t ldc; int c_row;
+    const void *A; int64_t lda;
+    const void *B; int64_t ldb;
+    void *C; int64_t ldc; int c_row;
     double alpha, beta;
     const double *a_diag;
     int upper_only;
+    int64_t kchunk;   // split-K chunk length (k when not split)
+    double *part;     // split-K partial tiles, m x n column-major per chunk
 };
 
-template <int AL, int BL>
-__global__ __launch_bounds__(256) void k_gemm_f64(Args g)
+// D layout of a 16x16 MFMA block: lane holds column (lane & 15); rows
+// (lane >> 4) + 4 r for FP64 and 4 (lane >> 4) + r for FP32, r = 0..3.
+template <typename TC>
+__device__ __forceinline__ int d_row(int lk, int r)
 {
+    if constexpr (sizeof(TC) == 8) return lk + 4 * r;
+    else return 4 * lk + r;
+}
+
+template <typename TC, typename TA, typename TB, typename TCS, int AL, int BL>
+__global__ __launch_bounds__(256) void k_gemm(Args g)
+{
+    using V4 = typename Acc<TC>::type;
+    constexpr int PAD = Acc<TC>::pad;
+    const TA *Ap = (const TA *)g.A;
+    const TB *Bp = (const TB *)g.B;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int64_t tm0 = (int64_t)blockIdx.x * TM;
     const int64_t tn0 = (int64_t)blockIdx.y * TN;
     if (g.upper_only && tm0 > tn0 + TN - 1) return;  // tile strictly below the diagonal
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = (kbeg + g.kchunk < g.k) ? kbeg + g.kchunk : g.k;
 
-    __shared__ double As[TK][TM + LDS_PAD];
-    __shared__ double Bs[TK][TN + LDS_PAD];
+    __shared__ TC As[TK][TM + PAD];
+    __shared__ TC Bs[TK][TN + PAD];
 
-    // global -> register staging: 4 elements of A and 4 of B per thread
-    double ra[4], rb[4];
+    TC ra[4], rb[4];
     auto fetch = [&](int64_t k0) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -64,7 +91,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(Args g)
             if constexpr (AL == 0) { ii = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
             const int64_t gi = tm0 + ii, gk = k0 + kk;
-            ra[p] = (gi < g.m && gk < g.k) ? load_op<AL>(g.A, g.lda, gi, gk, g.a_diag) : 0.0;
+            ra[p] = (gi < g.m && gk < kend) ? (TC)load_op<TA, AL>(Ap, g.lda, gi, gk, g.a_diag) : (TC)0;
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -72,7 +99,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(Args g)
             if constexpr (BL == 1) { jj = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
             const int64_t gk = k0 + kk, gj = tn0 + jj;
-            rb[p] = (gk < g.k && gj < g.n) ? load_op<BL>(g.B, g.ldb, gk, gj, nullptr) : 0.0;
+            rb[p] = (gk < kend && gj < g.n) ? (TC)load_op<TB, BL>(Bp, g.ldb, gk, gj, nullptr) : (TC)0;
         }
     };
     auto stash = [&]() {
@@ -93,23 +120,23 @@ __global__ __launch_bounds__(256) void k_gemm_f64(Args g)
     };
 
     const int wm = wave & 1, wn = wave >> 1;
-    dbl4 acc[2][2];
+    V4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
     const int li = lane & 15, lk = lane >> 4;
-    fetch(0);
-    for (int64_t k0 = 0; k0 < g.k; k0 += TK) {
+    if (kbeg < kend) fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
         __syncthreads();
         stash();
         __syncthreads();
-        if (k0 + TK < g.k) fetch(k0 + TK);
+        if (k0 + TK < kend) fetch(k0 + TK);
 #pragma unroll
         for (int kq = 0; kq < TK / 4; ++kq) {
             const int kr = kq * 4 + lk;
-            double av[2], bv[2];
+            TC av[2], bv[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) av[a] = As[kr][wm * 32 + a * 16 + li];
 #pragma unroll
@@ -117,55 +144,135 @@ __global__ __launch_bounds__(256) void k_gemm_f64(Args g)
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) {
+                    if constexpr (sizeof(TC) == 8)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                    else
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+                }
         }
     }
 
-    // D layout of the FP64 16x16 block: lane holds column (lane & 15) and
-    // rows (lane >> 4) + 4 r, r = 0..3 (checked on gfx950)
+    TCS *Cp = (TCS *)g.C;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = tm0 + wm * 32 + a * 16 + lk + 4 * r;
+                const int64_t i = tm0 + wm * 32 + a * 16 + d_row<TC>(lk, r);
                 const int64_t j = tn0 + wn * 32 + b * 16 + li;
                 if (i >= g.m || j >= g.n) continue;
+                if (g.part) {  // split-K partial: plain sum, alpha/beta applied by the reduction
+                    g.part[((int64_t)blockIdx.z * g.n + j) * g.m + i] = (double)acc[a][b][r];
+                    continue;
+                }
                 if (g.upper_only && i > j) continue;
-                double *cp = g.c_row ? &g.C[i * g.ldc + j] : &g.C[j * g.ldc + i];
-                double v = g.alpha * acc[a][b][r];
-                if (g.beta != 0.0) v += g.beta * *cp;
-                *cp = v;
+                TCS *cp = g.c_row ? &Cp[i * g.ldc + j] : &Cp[j * g.ldc + i];
+                double v = g.alpha * (double)acc[a][b][r];
+                if (g.beta != 0.0) v += g.beta * (double)*cp;
+                *cp = (TCS)v;
             }
 }
 
-template <int AL, int BL>
-int run(const Args &a, hipStream_t st)
+template <typename TCS>
+__global__ void k_splitk_reduce(const double *__restrict__ part, int nz, int64_t m, int64_t n, void *C,
+                                int64_t ldc, int c_row, double alpha, double beta, int upper_only)
 {
-    dim3 grid((unsigned)cdiv(a.m, TM), (unsigned)cdiv(a.n, TN));
-    hipLaunchKernelGGL((k_gemm_f64<AL, BL>), grid, dim3(256), 0, st, a);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * n) return;
+    const int64_t i = t % m, j = t / m;
+    if (upper_only && i > j) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * m * n + t];
+    TCS *Cp = (TCS *)C;
+    TCS *cp = c_row ? &Cp[i * ldc + j] : &Cp[j * ldc + i];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * (double)*cp;
+    *cp = (TCS)v;
+}
+
+template <typename TC, typename TA, typename TB, typename TCS, int AL, int BL>
+int run(const Args &a, int nz, hipStream_t st)
+{
+    dim3 grid((unsigned)cdiv(a.m, TM), (unsigned)cdiv(a.n, TN), (unsigned)nz);
+    hipLaunchKernelGGL((k_gemm<TC, TA, TB, TCS, AL, BL>), grid, dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+template <typename TC, typename TA, typename TB, typename TCS>
+int run_layout(const Args &a, int al, int bl, int nz, hipStream_t st)
+{
+    switch (al * 2 + bl) {
+        case 0: return run<TC, TA, TB, TCS, 0, 0>(a, nz, st);
+        case 1: return run<TC, TA, TB, TCS, 0, 1>(a, nz, st);
+        case 2: return run<TC, TA, TB, TCS, 1, 0>(a, nz, st);
+        case 3: return run<TC, TA, TB, TCS, 1, 1>(a, nz, st);
+        case 4:
+            if constexpr (sizeof(TA) == 8) return run<TC, TA, TB, TCS, 2, 0>(a, nz, st);
+            else return GSYEIG_EHIP;
+        case 5:
+            if constexpr (sizeof(TA) == 8) return run<TC, TA, TB, TCS, 2, 1>(a, nz, st);
+            else return GSYEIG_EHIP;
+        default: return GSYEIG_EHIP;
+    }
+}
+
+template <typename TC, typename TCS>
+int run_types(const Args &a, const GemmDesc &d, int nz, hipStream_t st)
+{
+    const int ta = d.a_f32, tb = d.b_f32;
+    if (!ta && !tb) return run_layout<TC, double, double, TCS>(a, d.a_layout, d.b_layout, nz, st);
+    if (!ta && tb) return run_layout<TC, double, float, TCS>(a, d.a_layout, d.b_layout, nz, st);
+    if (ta && !tb) return run_layout<TC, float, double, TCS>(a, d.a_layout, d.b_layout, nz, st);
+    return run_layout<TC, float, float, TCS>(a, d.a_layout, d.b_layout, nz, st);
 }
 
 }  // namespace
 
-int launch_gemm_f64(const GemmDesc &d, hipStream_t st)
+int launch_gemm(const GemmDesc &d, hipStream_t st)
 {
     if (d.m <= 0 || d.n <= 0) return 0;
-    Args a{d.m, d.n, d.k, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.c_layout == 1,
-           d.alpha, d.beta, d.a_diag, d.upper_only};
-    if (d.k <= 0) {  // C = beta C: run with a zero-length K loop
-        a.k = 0;
+    if (d.a_layout == 2 && d.a_f32) return GSYEIG_EHIP;
+    Args a{d.m, d.n, d.k > 0 ? d.k : 0, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.c_layout == 1,
+           d.alpha, d.beta, d.a_diag, d.upper_only, 0, nullptr};
+    int nz = 1;
+    if (d.splitk > 1 && d.part && a.k > 0) {
+        const int64_t kc = cdiv(cdiv(a.k, d.splitk), TK) * TK;
+        nz = (int)cdiv(a.k, kc);
+        a.kchunk = kc;
+        a.part = d.part;
+    } else {
+        a.kchunk = a.k;
     }
-    switch (d.a_layout * 2 + d.b_layout) {
-        case 0: return run<0, 0>(a, st);
-        case 1: return run<0, 1>(a, st);
-        case 2: return run<1, 0>(a, st);
-        case 3: return run<1, 1>(a, st);
-        case 4: return run<2, 0>(a, st);
-        case 5: return run<2, 1>(a, st);
-        default: return GSYEIG_EHIP;
+    if (nz == 1) {
+        a.part = nullptr;
+        a.kchunk = a.k;
     }
+    int rc;
+    if (d.f32) {
+        // FP32 compute: C stored FP64 or FP32
+        rc = d.c_f32 ? run_types<float, float>(a, d, nz, st) : run_types<float, double>(a, d, nz, st);
+    } else {
+        if (d.c_f32) return GSYEIG_EHIP;
+        rc = run_types<double, double>(a, d, nz, st);
+    }
+    if (rc || nz == 1) return rc;
+    const int64_t tot = d.m * d.n;
+    if (d.c_f32)
+        hipLaunchKernelGGL(k_splitk_reduce<float>, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, st, d.part, nz,
+                           d.m, d.n, d.C, d.ldc, (int)(d.c_layout == 1), d.alpha, d.beta, d.upper_only);
+    else
+        hipLaunchKernelGGL(k_splitk_reduce<double>, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, st, d.part, nz,
+                           d.m, d.n, d.C, d.ldc, (int)(d.c_layout == 1), d.alpha, d.beta, d.upper_only);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+int launch_gemm_f64(const GemmDesc &d, hipStream_t st) { return launch_gemm(d, st); }
+
+int64_t gemm_splitk_parts(const GemmDesc &d)
+{
+    if (d.splitk <= 1 || d.k <= 0) return 1;
+    const int64_t kc = cdiv(cdiv(d.k, d.splitk), TK) * TK;
+    return cdiv(d.k, kc);
 }

@@ -7,7 +7,8 @@
 //   column part  y_J += A_IJ^T x_I  (J > I; the diagonal tile is applied
 //                                    once, from full storage)
 // Partial results go to a scratch area and a second kernel sums them in a
-// fixed order, so the result is bitwise reproducible run to run.
+// fixed order, so the result is bitwise reproducible run to run.  A may be
+// stored in FP64 or FP32 (mixed mode); arithmetic and vectors are FP64.
 #include <vector>
 
 #include "internal.h"
@@ -16,7 +17,8 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A, int64_t lda,
+template <typename T>
+__global__ __launch_bounds__(256) void k_symv_tiles(const T *__restrict__ A, int64_t lda,
                                                     int64_t n, int nblk, int maxch,
                                                     const double *__restrict__ x,
                                                     const int2 *__restrict__ items,
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A
     const int64_t r0 = (int64_t)I * NB;
     const int c = 16 * w + (lane & 15);
     const int rg = lane >> 4;
-    const double *Arow = A + (r0 + rg) * lda;
+    const T *Arow = A + (r0 + rg) * lda;
 
     double a[SYMV_CH][16], xj[SYMV_CH];
 #pragma unroll
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const bool ok = colok && (r0 + rg + 4 * q < n);
-            a[t][q] = ok ? Arow[(int64_t)(4 * q) * lda + col] : 0.0;
+            a[t][q] = ok ? (double)Arow[(int64_t)(4 * q) * lda + col] : 0.0;
         }
         xj[t] = colok ? x[col] : 0.0;
     }
@@ -118,7 +120,8 @@ __global__ __launch_bounds__(256) void k_symv_reduce(const double *__restrict__ 
 
 }  // namespace
 
-int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)
+template <typename T>
+static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, const double *x, double *y)
 {
     const int nblk = (int)cdiv(n, NB);
     const int maxch = (int)cdiv(nblk, SYMV_CH);
@@ -138,11 +141,21 @@ int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const 
     void *pr, *pc;
     if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * maxch * NB, &pr))) return rc;
     if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &pc))) return rc;
-    hipLaunchKernelGGL(k_symv_tiles, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
+    hipLaunchKernelGGL(k_symv_tiles<T>, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
                        lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr,
                        (double *)pc);
     if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
                        (const double *)pc, nblk, maxch, n, y);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double *y)
+{
+    return launch_symv_t<double>(ctx, n, A, lda, x, y);
+}
+
+int launch_symv_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double *y)
+{
+    return launch_symv_t<float>(ctx, n, A, lda, x, y);
 }

@@ -316,15 +316,16 @@ __global__ __launch_bounds__(256) void k_tri_cluster(int64_t m, int64_t nwant,
     }
 }
 
-// nconv = #{ i : |beta_m| lastcomp[i] <= tol ||T|| },  ||T|| ~ max |theta|
+// nconv = #{ i in [i0, i0 + cnt) : |beta_m| lastcomp[i] <= tol ||T|| },
+// ||T|| ~ max |theta| over the nwant computed values and the opposite extreme
 __global__ __launch_bounds__(64) void k_conv_count(const double *theta, const double *lastcomp,
-                                                   const double *beta_m, int64_t nwant, double tol,
-                                                   int *nconv)
+                                                   const double *beta_m, int64_t nwant, int64_t i0,
+                                                   int64_t cnt, double tol, int *nconv)
 {
     const double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
     const double bm = fabs(*beta_m);
     int c = 0;
-    for (int64_t i = threadIdx.x; i < nwant; i += 64) c += (bm * lastcomp[i] <= tol * tn);
+    for (int64_t i = i0 + threadIdx.x; i < i0 + cnt; i += 64) c += (bm * lastcomp[i] <= tol * tn);
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if (threadIdx.x == 0) *nconv = c;
 }
@@ -359,9 +360,9 @@ int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64
 }
 
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
-                      int64_t nwant, double tol, int *nconv, hipStream_t st)
+                      int64_t nwant, int64_t i0, int64_t cnt, double tol, int *nconv, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, tol,
+    hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, i0, cnt, tol,
                        nconv);
     return ok();
 }

@@ -31,7 +31,8 @@ namespace {
 using namespace chain;
 
 // ------------------------------------------------------------------ KI1
-__global__ __launch_bounds__(1024) void k_trsv_sb_n(const double *__restrict__ U, int64_t ldu,
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_sb_n(const T *__restrict__ U, int64_t ldu,
                                                     int64_t n, int nblk,
                                                     const double *__restrict__ Uinv,
                                                     const double *__restrict__ N,
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_n(const double *__restrict__ U
     const int jlo = (S + 2) * TPS;
     const int ntile = nblk - jlo;
     if (ntile > 0) {
-        const double *Ur = U + (r0 + 4 * w) * ldu;  // rows of a non-last tile exist
+        const T *Ur = U + (r0 + 4 * w) * ldu;  // rows of a non-last tile exist
         const int64_t cmax = n - 1;
         auto colof = [&](int t) {
             const int j = (t < ntile) ? nblk - 1 - t : jlo;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_n(const double *__restrict__ U
         for (int g = 0; g < GRP2; ++g) {
             const int64_t cc = colof(g);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cur[g][r] = Ur[(int64_t)r * ldu + cc];
+            for (int r = 0; r < 4; ++r) cur[g][r] = (double)Ur[(int64_t)r * ldu + cc];
         }
         for (int t0 = 0; t0 < ntile; t0 += GRP2) {
             unsigned long long v[GRP2];
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_n(const double *__restrict__ U
             for (int g = 0; g < GRP2; ++g) {
                 const int64_t cc = colof(t0 + GRP2 + g);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) nxt[g][r] = Ur[(int64_t)r * ldu + cc];
+                for (int r = 0; r < 4; ++r) nxt[g][r] = (double)Ur[(int64_t)r * ldu + cc];
             }
 #pragma unroll
             for (int g = 0; g < GRP2; ++g) {
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_n(const double *__restrict__ U
 }
 
 // ------------------------------------------------------------------ KI3
-__global__ __launch_bounds__(1024) void k_trsv_sb_t(const double *__restrict__ U, int64_t ldu,
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_sb_t(const T *__restrict__ U, int64_t ldu,
                                                     int64_t n, int nblk,
                                                     const double *__restrict__ UinvT,
                                                     const double *__restrict__ Nt,
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_t(const double *__restrict__ U
         for (int g = 0; g < GRP2; ++g) {
             const int64_t rr = rowof(g);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cur[g][r] = U[(rr + r) * ldu + colc];
+            for (int r = 0; r < 4; ++r) cur[g][r] = (double)U[(rr + r) * ldu + colc];
         }
         for (int t0 = 0; t0 < ntile; t0 += GRP2) {
             const int p = l & 7;  // lane p < 8 polls value p&3 of tile p>>2 of the group
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_t(const double *__restrict__ U
             for (int g = 0; g < GRP2; ++g) {
                 const int64_t rr = rowof(t0 + GRP2 + g);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) nxt[g][r] = U[(rr + r) * ldu + colc];
+                for (int r = 0; r < 4; ++r) nxt[g][r] = (double)U[(rr + r) * ldu + colc];
             }
             const double zmine = settle(pv, stage + prow, &ctl->err);
 #pragma unroll
@@ -309,10 +311,11 @@ size_t trsv_sb_bytes(int64_t n)
     return 4 * sizeof(double) * (size_t)nsb * SBR * SBR;
 }
 
-// Fills [Uinv | UinvT | N | N'] (each nsb blocks of SBR x SBR, row-major) for
-// the upper factor U whose 64x64 diagonal-block inverses are in Dinv.
-int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
-                   hipStream_t st)
+// Fills [Uinv | UinvT | N | N'] (each nsb blocks of SBR x SBR, row-major,
+// FP64) for the upper factor U (stored FP64 or FP32) whose 64x64
+// diagonal-block inverses are in Dinv.
+template <typename T>
+static int make_sb_t(const T *U, int64_t ldu, int64_t n, const double *Dinv, double *sb, hipStream_t st)
 {
     const int64_t nsb = cdiv(n, SBR);
     const int64_t blk = (int64_t)SBR * SBR;
@@ -325,7 +328,13 @@ int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, 
         double *X = UinvT + S * blk;
         hipLaunchKernelGGL(k_identity_sb, dim3((unsigned)cdiv(blk, 256)), dim3(256), 0, st, X, r);
         if (ok()) return GSYEIG_EHIP;
-        int rc = launch_backsolve(U + s0 * ldu + s0, ldu, r, r, Dinv + (s0 / NB) * NB * NB, X, SBR, st);
+        int rc;
+        if constexpr (sizeof(T) == 8)
+            rc = launch_backsolve((const double *)U + s0 * ldu + s0, ldu, r, r, Dinv + (s0 / NB) * NB * NB, X,
+                                  SBR, st);
+        else
+            rc = launch_backsolve_f32((const float *)U + s0 * ldu + s0, ldu, r, r, Dinv + (s0 / NB) * NB * NB,
+                                      X, SBR, st);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(k_transpose_sb, dim3(TPS * TPS, (unsigned)nsb), dim3(256), 0, st, UinvT, Uinv);
@@ -338,7 +347,7 @@ int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, 
             GemmDesc d{};
             d.m = r; d.n = rn; d.k = r;
             d.A = Uinv + S * blk; d.lda = SBR; d.a_layout = 1;
-            d.B = U + s0 * ldu + s0 + SBR; d.ldb = ldu; d.b_layout = 1;
+            d.B = U + s0 * ldu + s0 + SBR; d.ldb = ldu; d.b_layout = 1; d.b_f32 = sizeof(T) == 4;
             d.C = Nn + S * blk; d.ldc = SBR; d.c_layout = 1;
             d.alpha = 1.0; d.beta = 0.0;
             int rc = launch_gemm_f64(d, st);
@@ -348,7 +357,7 @@ int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, 
             GemmDesc d{};
             d.m = r; d.n = SBR; d.k = r;
             d.A = UinvT + S * blk; d.lda = SBR; d.a_layout = 1;
-            d.B = U + (s0 - SBR) * ldu + s0; d.ldb = ldu; d.b_layout = 0;
+            d.B = U + (s0 - SBR) * ldu + s0; d.ldb = ldu; d.b_layout = 0; d.b_f32 = sizeof(T) == 4;
             d.C = Nt + S * blk; d.ldc = SBR; d.c_layout = 1;
             d.alpha = 1.0; d.beta = 0.0;
             int rc = launch_gemm_f64(d, st);
@@ -358,22 +367,81 @@ int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, 
     return 0;
 }
 
-int launch_trsv_sb_n(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
-                     double *x, double *rstage, PCtl *ctl, hipStream_t st)
+int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
+                   hipStream_t st)
+{
+    return make_sb_t<double>(U, ldu, n, Dinv, sb, st);
+}
+
+int launch_make_sb_f32(const float *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
+                       hipStream_t st)
+{
+    return make_sb_t<float>(U, ldu, n, Dinv, sb, st);
+}
+
+template <typename T>
+static int trsv_sb_n_t(const T *U, int64_t ldu, int64_t n, const double *sb, const double *b, double *x,
+                       double *rstage, PCtl *ctl, hipStream_t st)
 {
     const int nblk = (int)cdiv(n, NB);
     const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
-    hipLaunchKernelGGL(k_trsv_sb_n, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, sb,
+    hipLaunchKernelGGL(k_trsv_sb_n<T>, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, sb,
                        sb + 2 * nsb * blk, b, x, rstage, ctl);
     return ok();
+}
+
+template <typename T>
+static int trsv_sb_t_t(const T *U, int64_t ldu, int64_t n, const double *sb, const double *b, double *x,
+                       double *rstage, PCtl *ctl, hipStream_t st)
+{
+    const int nblk = (int)cdiv(n, NB);
+    const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
+    hipLaunchKernelGGL(k_trsv_sb_t<T>, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, sb + nsb * blk,
+                       sb + 3 * nsb * blk, b, x, rstage, ctl);
+    return ok();
+}
+
+int launch_trsv_sb_n(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                     double *x, double *rstage, PCtl *ctl, hipStream_t st)
+{
+    return trsv_sb_n_t<double>(U, ldu, n, sb, b, x, rstage, ctl, st);
 }
 
 int launch_trsv_sb_t(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
                      double *x, double *rstage, PCtl *ctl, hipStream_t st)
 {
-    const int nblk = (int)cdiv(n, NB);
-    const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
-    hipLaunchKernelGGL(k_trsv_sb_t, dim3(nblk), dim3(1024), 0, st, U, ldu, n, nblk, sb + nsb * blk,
-                       sb + 3 * nsb * blk, b, x, rstage, ctl);
-    return ok();
+    return trsv_sb_t_t<double>(U, ldu, n, sb, b, x, rstage, ctl, st);
+}
+
+int launch_trsv_sb_n_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                         double *x, double *rstage, PCtl *ctl, hipStream_t st)
+{
+    return trsv_sb_n_t<float>(U, ldu, n, sb, b, x, rstage, ctl, st);
+}
+
+int launch_trsv_sb_t_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
+                         double *x, double *rstage, PCtl *ctl, hipStream_t st)
+{
+    return trsv_sb_t_t<float>(U, ldu, n, sb, b, x, rstage, ctl, st);
+}
+
+// FP32 copy of an FP64 matrix (rows x cols, leading dimensions lds / ldd)
+__global__ void k_to_f32(const double *__restrict__ src, int64_t lds, float *__restrict__ dst,
+                         int64_t ldd, int64_t rows, int64_t cols)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.y;
+    if (c < cols && r < rows) dst[r * ldd + c] = (float)src[r * lds + c];
+}
+
+int launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
+                  hipStream_t st)
+{
+    for (int64_t r0 = 0; r0 < rows; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, rows - r0);
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)cdiv(cols, 256), (unsigned)nr), dim3(256), 0, st,
+                           src + r0 * lds, lds, dst + r0 * ldd, ldd, nr, cols);
+        if (ok()) return GSYEIG_EHIP;
+    }
+    return 0;
 }

@@ -51,7 +51,8 @@ def test_version_and_defaults(gs):
     o = gs.gsyeig_opts_default()
     assert (o.prec, o.block, o.which, o.invert) == (0, 1, 0, 0)
     assert o.tol == 1e-12 and o.check_every == 25 and o.seed == 6374 and not o.v0
-    assert ctypes.sizeof(gs.gsyeig_opts) == 64 and o.profile_every == 0
+    assert ctypes.sizeof(gs.gsyeig_opts) == 96 and o.profile_every == 0
+    assert (o.eta_tol, o.refine_iters, o.refine_inner, o.guard) == (1e-10, 10, 20, 0)
 
 
 def test_workspace_size(gs):
@@ -61,12 +62,21 @@ def test_workspace_size(gs):
     assert b >= 16384 * (12000 + 1) * 8
     assert gs.gsyeig_workspace_size(0, 1)[0] == -1
     assert gs.gsyeig_workspace_size(10, 11)[0] == -2
+    # mixed mode adds the FP32 copies of A and U (4 bytes each per entry)
+    o = gs.gsyeig_opts_default()
+    o.prec = gs.GSYEIG_MIXED
+    rc, bm = gs.gsyeig_workspace_size(16384, 100, o)
+    assert rc == 0 and bm >= b + 2 * 4 * 16384 * 16384
 
 
 def test_null_context_is_rejected_without_gpu(gs):
     assert gs.gsyeig_solve(None, 10, 2, 1, 10, 1, 10, None, 1, 1, 10)[0] == -1
     assert gs.gsyeig_potrf(None, 10, 1, 10) == -1
     assert gs.gsyeig_trsv(None, 10, 1, 10, 0, 1, 1) == -1
+    assert gs.gsyeig_trsv_lp(None, 10, 1, 10, 0, 1, 1) == -1
+    assert gs.gsyeig_trsm_lp(None, 10, 1, 10, 0, 2, 1, 10, 1, 10) == -1
+    assert gs.gsyeig_syev_small(None, 10, 1, 10, 2, 0, 1, 1, 10) == -1
+    assert gs.gsyeig_refine(None, 10, 2, 4, 1, 10, 1, 10, 1, 10, None, 1, 10, 1, 1, 10)[0] == -1
     assert gs.gsyeig_destroy(None) == -1
     assert gs.lib().gsyeig_opts_default(None) == -1
 
