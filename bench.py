@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 CONFIGS = {
     0: dict(n=512, s=10, law="spaced", label="known-spectrum pencil n=512 s=10, FP64 single-vector KI"),
     1: dict(n=16384, s=100, law="spaced", label="known-spectrum pencil n=16384 s=100, FP64 single-vector KI"),
+    2: dict(n=32768, s=200, law="clustered",
+            label="known-spectrum pencil n=32768 s=200, clustered spectrum, mixed FP32 sweeps + FP64 refinement"),
     4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n), FP64"),
 }
 HBM_PEAK_GBS = 8000.0
@@ -31,14 +33,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_target):
+def cpu_baseline(n_target, law="spaced"):
     """The oracle (plain C, FP64) on a bounded sample: a full solve at n = 2048
     of the same generator, scaled by (n_target / 2048)^3 (every stage is O(n^3))."""
     import gen
     import oracle
 
     n, s = 2048, 13
-    d = gen.known_spectrum(n, seed=gen.BASE_SEED, stream=(1, 0, 99))
+    d = gen.known_spectrum(n, law, seed=gen.BASE_SEED, stream=(1, 0, 99))
     oracle.lib()
     t0 = time.perf_counter()
     oracle.gsyeig(d["A"], d["B"], s)
@@ -59,6 +61,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=512, help="instances for --config 4")
     ap.add_argument("--streams", type=int, default=8, help="worker streams for --config 4")
+    ap.add_argument("--n", type=int, default=0, help="override n (exploration; the config label then says so)")
+    ap.add_argument("--s", type=int, default=0, help="override s")
+    ap.add_argument("--no-fp64-compare", action="store_true", help="--config 2: skip the FP64 solve")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -73,9 +78,15 @@ def main():
     import gen
     import paper_1111_6374_amd as gs
 
-    cfg = CONFIGS[args.config]
+    cfg = dict(CONFIGS[args.config])
+    if args.n or args.s:
+        cfg["n"] = args.n or cfg["n"]
+        cfg["s"] = args.s or cfg["s"]
+        cfg["label"] += f" (reduced to n={cfg['n']} s={cfg['s']})"
     if args.config == 4:
         return bench_batched(args, cfg)
+    if args.config == 2:
+        return bench_mixed(args, cfg)
     n, s = cfg["n"], cfg["s"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -163,6 +174,114 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(args, cfg):
+    """Mixed precision (FP32 sweeps + FP64 refinement) on the clustered
+    known-spectrum pencil, with the plain FP64 solve of the same input timed
+    beside it on the same GPU."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1111_6374_amd as gs
+
+    n, s = cfg["n"], cfg["s"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating n={n} s={s} law={cfg['law']}")
+    t0 = time.perf_counter()
+    inst = gen.known_spectrum_device(n, cfg["law"], seed=gen.BASE_SEED + 2, stream=(2, 0, 0), device=dev,
+                                     keep_factors=False)
+    A, B0 = inst["A"], inst["B"]
+    lam_true = np.sort(inst["lam"])[:s]
+    B = torch.empty_like(B0)
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    solver = gs.Solver()
+    Lam = torch.empty(s, dtype=torch.float64, device=dev)
+    X = torch.empty(s, n, dtype=torch.float64, device=dev)
+
+    def run(prec):
+        o = gs.gsyeig_opts_default()
+        o.prec = prec
+        o.profile_every = args.profile_every
+        B.copy_(B0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, info = gs.gsyeig_solve(solver.ctx, n, s, A, n, B, n, o, Lam, X, n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if rc:
+            raise gs.GsyeigError("gsyeig_solve", rc)
+        return dt, info
+
+    def show(tag, dt, inf):
+        log(f"{tag}: {dt:.2f} s (GS1 {inf.t_gs1_ms:.0f} ms, KI {inf.t_ki_ms:.0f}, KI5 {inf.t_ki5_ms:.0f}, "
+            f"BT1 {inf.t_bt1_ms:.0f}, refine {inf.t_refine_ms:.0f}, check {inf.t_check_ms:.0f}) m={inf.steps} "
+            f"eta={inf.eta_max:.2e} eta1={inf.eta_phase1:.2e} rounds={inf.refine_iters} "
+            f"block_ops={inf.block_applies}x{inf.block_cols}")
+
+    for w in range(args.warmup):
+        dt, inf = run(gs.GSYEIG_MIXED)
+        show("warmup mixed", dt, inf)
+    times, infos = [], []
+    for k in range(args.steps):
+        dt, inf = run(gs.GSYEIG_MIXED)
+        show(f"step {k} mixed", dt, inf)
+        times.append(dt)
+        infos.append(inf)
+    lam_mixed = Lam.cpu().numpy()
+    mx = float(np.max(np.abs(inst["lam"])))
+    e_lam = float(np.max(np.abs(lam_mixed - lam_true)) / mx)
+    value = sum(times) / len(times)
+    last = infos[-1]
+    fp64 = None
+    if not args.no_fp64_compare:
+        dt64, inf64 = run(gs.GSYEIG_FP64)
+        show("fp64", dt64, inf64)
+        lam64 = Lam.cpu().numpy()
+        fp64 = {"time_s": dt64, "lanczos_steps": int(inf64.steps), "eta_max": inf64.eta_max,
+                "e_lambda_vs_known": float(np.max(np.abs(lam64 - lam_true)) / mx),
+                "lambda_diff_vs_mixed": float(np.max(np.abs(lam64 - lam_mixed)) / mx),
+                "stages_ms": {"gs1": inf64.t_gs1_ms, "ki_loop": inf64.t_ki_ms, "ki5": inf64.t_ki5_ms,
+                              "bt1": inf64.t_bt1_ms, "check": inf64.t_check_ms},
+                "speedup_of_mixed": dt64 / value}
+    samples = sum(i.prof_samples for i in infos)
+    t1 = sum(i.t_ki1_ms_sum for i in infos) / max(samples, 1)
+    t2 = sum(i.t_ki2_ms_sum for i in infos) / max(samples, 1)
+    t3 = sum(i.t_ki3_ms_sum for i in infos) / max(samples, 1)
+    tri32 = 4.0 * n * (n + 1) / 2
+    vec = 8.0 * 2 * n
+    trsv_ms = 0.5 * (t1 + t3)
+    trsv_gbs = (tri32 + vec) / (trsv_ms * 1e-3) / 1e9 if trsv_ms > 0 else None
+    symv_gbs = (tri32 + vec) / (t2 * 1e-3) / 1e9 if t2 > 0 else None
+    out = {
+        "metric": "time-to-s-eigenpairs", "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "mixed",
+                   "block": 1, "lanczos_steps": int(last.steps), "refine_rounds": int(last.refine_iters),
+                   "block_cols": int(last.block_cols), "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None, "traffic": None,
+                     "kernel": "k_trsv_sb_n/k_trsv_sb_t on FP32 U (KI1/KI3)", "avg_launch_ms": trsv_ms,
+                     "algorithmic_bytes_per_launch": tri32 + vec},
+        "kernels": {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
+                    "samples": samples},
+        "stages_ms": {"gs1": last.t_gs1_ms, "ki_loop": last.t_ki_ms, "ki5": last.t_ki5_ms, "bt1": last.t_bt1_ms,
+                      "refine": last.t_refine_ms, "check": last.t_check_ms, "total": last.t_total_ms},
+        "refinement": {"eta_after_first_rr": last.eta_phase1, "rounds": int(last.refine_iters),
+                       "fp32_block_applications": int(last.block_applies), "block_cols": int(last.block_cols)},
+        "parity": {"e_lambda_vs_known": e_lam, "eta_max": last.eta_max, "omega": last.omega, "rho_F": last.rho_f,
+                   "pass": bool(e_lam <= 1e-10 and last.eta_max <= 1e-10)},
+        "fp64_same_input": fp64,
+    }
+    solver.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(n, cfg["law"])
     print(json.dumps(out), flush=True)
 
 

@@ -240,6 +240,56 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     return 0;
 }
 
+static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double *Dinv, int *info_d);
+
+// Makes the nw columns of S (m x nw, column-major) orthonormal by Cholesky
+// QR applied twice: G = S^T S = R^T R, S <- S R^-1 (FP64 GEMMs on the matrix
+// cores, small Cholesky and triangular inverse by the GS1 kernels).  Used
+// on inverse-iteration eigenvectors of T_m, whose mutual overlaps are tiny
+// except inside clusters of close eigenvalues; there any orthonormal basis
+// of the computed vectors is as good.  *info_d != 0 if G was not positive
+// definite or if two columns overlapped by more than 1e-8 (the caller then
+// falls back to sequential Gram-Schmidt with extra inverse-iteration solves).
+static int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d)
+{
+    const int64_t nwr = cdiv(nw, NB) * NB;
+    const int64_t sk = std::max<int64_t>(1, std::min<int64_t>(32, cdiv(m, 1024)));
+    const size_t need = sizeof(double) * ((size_t)nw * nw * 2 + (size_t)nwr * NB + (size_t)m * nw +
+                                          (size_t)sk * nw * nw + 64);
+    void *p;
+    TRY(ws_get(ctx, WS_RITZ, need, &p));
+    double *G = (double *)p, *Ri = G + nw * nw, *Dv = Ri + nw * nw, *T = Dv + nwr * NB, *part = T + m * nw;
+    HIP_TRY(hipMemsetAsync(info_d, 0, sizeof(int), ctx->stream));
+    int *info2 = info_d + 1;
+    for (int pass = 0; pass < 2; ++pass) {
+        GemmDesc g{};
+        g.m = nw; g.n = nw; g.k = m;
+        g.A = S; g.lda = lds; g.a_layout = 1;   // A(i, t) = S(t, i)
+        g.B = S; g.ldb = lds; g.b_layout = 0;
+        g.C = G; g.ldc = nw; g.c_layout = 1;    // symmetric: either layout
+        g.alpha = 1.0; g.beta = 0.0;
+        g.splitk = (int)sk; g.part = part;
+        TRY(launch_gemm(g, ctx->stream));
+        // overlaps beyond 1e-8 mean near-equal Ritz values whose vectors need
+        // the sequential treatment (extra solves inside the cluster)
+        if (pass == 0) TRY(launch_flag_offdiag(G, nw, 1e-8, info_d, ctx->stream));
+        TRY(potrf_core(ctx, nw, G, nw, Dv, info2));
+        TRY(launch_accum_info(info2, info_d, ctx->stream));
+        // Ri = R^-1 (column-major; R is G's upper triangle, row-major)
+        TRY(launch_identity(Ri, nw, nw, ctx->stream));
+        TRY(launch_backsolve(G, nw, nw, nw, Dv, Ri, nw, ctx->stream));
+        GemmDesc u{};
+        u.m = m; u.n = nw; u.k = nw;
+        u.A = S; u.lda = lds; u.a_layout = 0;
+        u.B = Ri; u.ldb = nw; u.b_layout = 0;
+        u.C = T; u.ldc = m; u.c_layout = 0;
+        u.alpha = 1.0; u.beta = 0.0;
+        TRY(launch_gemm(u, ctx->stream));
+        TRY(launch_blk_copy(T, m, S, lds, m, nw, ctx->stream));
+    }
+    return 0;
+}
+
 struct LzBufs {
     double *z, *tmp, *red, *red2, *h, *normpart;
 };
@@ -294,9 +344,13 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     void *p;
     TRY(ws_get(ctx, WS_V, sizeof(double) * (size_t)ldv * (size_t)(mmax + 1), &p));
     double *V = (double *)p;
-    // T: alpha (mmax), beta (mmax), theta (nvec+1), lastcomp (nvec)
-    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * nvec + 16), &p));
+    // T: alpha (mmax), beta (mmax), theta (nvec+1), lastcomp (nvec), pre-check (2 x 32)
+    TRY(ws_get(ctx, WS_T, sizeof(double) * (size_t)(2 * mmax + 2 * nvec + 16 + 64), &p));
     double *alpha = (double *)p, *beta = alpha + mmax, *theta = beta + mmax, *lastc = theta + nvec + 1;
+    double *theta_q = lastc + nvec + 8, *lastc_q = theta_q + 32;
+    // pre-check: the q innermost wanted Ritz values converge last; only when
+    // they all meet tol is the full set of s checked
+    const int64_t q = std::min<int64_t>(s, 16);
     TRY(ws_get(ctx, WS_TRI, sizeof(double) * (size_t)nvec * 7 * (size_t)mmax, &p));
     double *tri = (double *)p;
     LzBufs b;
@@ -326,9 +380,19 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
         m = k + 1;
         checked_at_m = false;
         if (m >= nvec && (m % every == 0 || m == mmax)) {
+            if (q < s && m < mmax) {
+                const int64_t first = o->which ? m - s : s - q;
+                TRY(launch_tri_bisect_range(alpha, beta, m, first, q, o->which, theta_q, ctx->stream));
+                TRY(launch_tri_vectors(alpha, beta, m, q, theta_q, nullptr, 0, tri, 0, lastc_q, ctx->stream));
+                TRY(launch_conv_count(theta_q, lastc_q, beta + (m - 1), q, 0, q, 1, o->tol, nconv_d, ctx->stream));
+                HIP_TRY(hipMemcpyAsync(nconv_h, nconv_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIP_TRY(hipStreamSynchronize(ctx->stream));
+                TRY(prof_harvest(ctx));
+                if (*nconv_h < q) continue;
+            }
             TRY(launch_tri_bisect(alpha, beta, m, nvec, o->which, theta, ctx->stream));
             TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, nullptr, 0, tri, 0, lastc, ctx->stream));
-            TRY(launch_conv_count(theta, lastc, beta + (m - 1), nvec, w0, s, o->tol, nconv_d, ctx->stream));
+            TRY(launch_conv_count(theta, lastc, beta + (m - 1), nvec, w0, s, 0, o->tol, nconv_d, ctx->stream));
             HIP_TRY(hipMemcpyAsync(nconv_h, nconv_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));
             TRY(prof_harvest(ctx));
@@ -344,7 +408,13 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     // Ritz vectors: S (m x nvec) by inverse iteration, Y = V_m S
     TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)nvec, &p));
     double *S = (double *)p;
-    TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
+    TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 0, lastc, ctx->stream));
+    int *oinfo_d = (int *)ctx->dscal + 24;
+    TRY(orthonormalise_cols(ctx, m, nvec, S, m, oinfo_d));
+    HIP_TRY(hipMemcpyAsync(nconv_h, oinfo_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (*nconv_h != 0)  // Gram matrix not positive definite: sequential Gram-Schmidt in clusters
+        TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
     GemmDesc d{};
     d.m = n; d.n = nvec; d.k = m;
     d.A = V; d.lda = ldv; d.a_layout = 0;
@@ -364,14 +434,10 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     return 0;
 }
 
-// GS1: B = U^T U in place (upper triangle), Dinv blocks into WS_DINV.
-static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double **Dinv_out,
-                         int *info_d)
+// Blocked right-looking Cholesky B = U^T U of the upper triangle in place
+// (FP64), diagonal-block inverses into Dinv (cdiv(n, 64) blocks of 64x64).
+static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double *Dinv, int *info_d)
 {
-    void *p;
-    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
-    double *Dinv = (double *)p;
-    *Dinv_out = Dinv;
     HIP_TRY(hipMemsetAsync(info_d, 0, sizeof(int), ctx->stream));
     const int64_t nblk = cdiv(n, NB);
     for (int64_t kb = 0; kb < nblk; ++kb) {
@@ -399,6 +465,18 @@ static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, dou
         sd.upper_only = 1;
         TRY(launch_gemm_f64(sd, ctx->stream));
     }
+    return 0;
+}
+
+// GS1: B = U^T U in place (upper triangle), Dinv blocks into WS_DINV.
+static int potrf_enqueue(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double **Dinv_out,
+                         int *info_d)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    *Dinv_out = Dinv;
+    TRY(potrf_core(ctx, n, B, ldb, Dinv, info_d));
     return prepare_solves(ctx, n, B, ldb, Dinv);
 }
 

@@ -58,6 +58,7 @@ enum WsSlot {
     WS_A32,        // FP32 copy of A (mixed mode)
     WS_U32,        // FP32 Cholesky factor (mixed mode)
     WS_REFINE,     // blocks and small matrices of the FP64 refinement
+    WS_RITZ,       // orthonormalisation of the Ritz coefficient matrix
     WS_COUNT
 };
 
@@ -180,8 +181,12 @@ int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_
 int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64_t nwant,
                        const double *theta, double *S, int64_t lds, double *scratch, int clustered,
                        double *lastcomp, hipStream_t st);
+int launch_tri_bisect_range(const double *alpha, const double *beta, int64_t m, int64_t first,
+                            int64_t count, int which, double *theta, hipStream_t st);
+// tn_extra = 1: theta[nwant + 1] also enters the ||T|| estimate
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
-                      int64_t nwant, int64_t i0, int64_t cnt, double tol, int *nconv, hipStream_t st);
+                      int64_t nwant, int64_t i0, int64_t cnt, int tn_extra, double tol, int *nconv,
+                      hipStream_t st);
 
 // mixed-precision refinement (k_refine.hip)
 struct RefineOp {          // the FP32 operator C~ = U~^-T A~ U~^-1
@@ -207,6 +212,9 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
                        int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st);
 int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
                     hipStream_t st);
+int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st);   // r x r identity, column-major
+int launch_accum_info(const int *src, int *dst, hipStream_t st);        // *dst = *src if *dst == 0
+int launch_flag_offdiag(const double *G, int64_t r, double thresh, int *flag, hipStream_t st);
 size_t syev_small_scratch(int64_t N, int64_t nwant);
 int syev_small(int64_t N, double *H, int64_t nwant, int which, double *w, double *Q, double *scratch,
                hipStream_t st);

@@ -255,6 +255,29 @@ __global__ __launch_bounds__(256) void k_eta(const double *r2, const double *x2,
     }
 }
 
+__global__ void k_identity(double *X, int64_t ld, int64_t r)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= r * r) return;
+    const int64_t i = t % r, j = t / r;
+    X[j * ld + i] = (i == j) ? 1.0 : 0.0;
+}
+
+// *flag = -1 if any |G_ij - delta_ij| > thresh (G: r x r)
+__global__ void k_flag_offdiag(const double *G, int64_t r, double thresh, int *flag)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= r * r) return;
+    const int64_t i = t % r, j = t / r;
+    const double d = G[t] - ((i == j) ? 1.0 : 0.0);
+    if (fabs(d) > thresh || d != d) atomicCAS(flag, 0, -1);
+}
+
+__global__ void k_accum_info(const int *src, int *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *src != 0 && *dst == 0) *dst = *src;
+}
+
 // ||A||_F from the row partials of k_fro_parts
 __global__ void k_sum_sqrt(const double *part, int np, double *out)
 {
@@ -478,6 +501,24 @@ int gemm_mat(const void *M, int64_t ldm, int m_f32, int f32, const double *X, in
 }  // namespace
 
 // --------------------------------------------------------------- exported
+
+int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_identity, dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, st, X, ld, r);
+    return ok();
+}
+
+int launch_flag_offdiag(const double *G, int64_t r, double thresh, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flag_offdiag, dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, st, G, r, thresh, flag);
+    return ok();
+}
+
+int launch_accum_info(const int *src, int *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_accum_info, dim3(1), dim3(64), 0, st, src, dst);
+    return ok();
+}
 
 int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
                     hipStream_t st)

@@ -17,8 +17,7 @@
 
 namespace {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_symv_tiles(const T *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void k_symv_tiles(const double *__restrict__ A, int64_t lda,
                                                     int64_t n, int nblk, int maxch,
                                                     const double *__restrict__ x,
                                                     const int2 *__restrict__ items,
@@ -33,7 +32,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const T *__restrict__ A, int
     const int64_t r0 = (int64_t)I * NB;
     const int c = 16 * w + (lane & 15);
     const int rg = lane >> 4;
-    const T *Arow = A + (r0 + rg) * lda;
+    const double *Arow = A + (r0 + rg) * lda;
 
     double a[SYMV_CH][16], xj[SYMV_CH];
 #pragma unroll
@@ -44,7 +43,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const T *__restrict__ A, int
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const bool ok = colok && (r0 + rg + 4 * q < n);
-            a[t][q] = ok ? (double)Arow[(int64_t)(4 * q) * lda + col] : 0.0;
+            a[t][q] = ok ? Arow[(int64_t)(4 * q) * lda + col] : 0.0;
         }
         xj[t] = colok ? x[col] : 0.0;
     }
@@ -87,6 +86,108 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const T *__restrict__ A, int
         const int ch = (J0 - I) / SYMV_CH;
         Pr[((int64_t)I * maxch + ch) * NB + tid] =
             s_part[0][tid] + s_part[1][tid] + s_part[2][tid] + s_part[3][tid];
+    }
+}
+
+// The same work items with A stored FP32.  Each lane loads two adjacent
+// columns (8 bytes) and 32 lanes cover a whole 64-column tile row (two full
+// 128-byte lines), so one wave instruction reads two complete tile rows:
+// lane & 31 picks the column pair, rg = 2 w + (lane >> 5) one of 8 row
+// groups (rows rg + 8 q, q < 8).  Column partials of the four waves are
+// folded in LDS in a fixed order.  Every load is issued unconditionally from
+// a clamped in-bounds address and masked afterwards, so the loads of a work
+// item are all in flight together.  PAIR (lda even): 8-byte pair loads; a
+// pair that starts inside a row of length lda >= n+1 stays inside the row.
+template <bool PAIR>
+__global__ __launch_bounds__(256) void k_symv_tiles_f32(const float *__restrict__ A, int64_t lda,
+                                                        int64_t n, int nblk, int maxch,
+                                                        const double *__restrict__ x,
+                                                        const int2 *__restrict__ items,
+                                                        double *__restrict__ Pr,
+                                                        double *__restrict__ Pc)
+{
+    __shared__ double s_col[4][NB];
+    __shared__ double s_row[NB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int2 it = items[blockIdx.x];
+    const int I = it.x, J0 = it.y;
+    const int J1 = (J0 + SYMV_CH < nblk) ? J0 + SYMV_CH : nblk;
+    const int64_t r0 = (int64_t)I * NB;
+    const int c = 2 * (lane & 31);          // first of the lane's two columns in the tile
+    const int rg = 2 * w + (lane >> 5);     // row group: rows rg + 8 q
+    float2 a[SYMV_CH][8];  // kept FP32 in registers, widened at the multiply
+    double xj[SYMV_CH][2];
+#pragma unroll
+    for (int t = 0; t < SYMV_CH; ++t) {
+        const int J = J0 + t;
+        const int64_t col = (int64_t)J * NB + c;
+        const bool live = J < J1;
+        const bool c0ok = live && col < n, c1ok = live && col + 1 < n;
+        const int64_t cc = c0ok ? col : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t row = r0 + rg + 8 * q;
+            const bool rok = row < n;
+            const float *p = A + (rok ? row : 0) * lda + cc;
+            float2 v;
+            if constexpr (PAIR) {
+                v = *reinterpret_cast<const float2 *>(p);
+            } else {
+                v.x = p[0];
+                v.y = p[c1ok ? 1 : 0];
+            }
+            a[t][q].x = (rok && c0ok) ? v.x : 0.0f;
+            a[t][q].y = (rok && c1ok) ? v.y : 0.0f;
+        }
+        xj[t][0] = c0ok ? x[col] : 0.0;
+        xj[t][1] = c1ok ? x[col + 1] : 0.0;
+    }
+    double xi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xi[q] = (r0 + rg + 8 * q < n) ? x[r0 + rg + 8 * q] : 0.0;
+
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < SYMV_CH; ++t) {
+        const int J = J0 + t;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            acc[q] = fma((double)a[t][q].y, xj[t][1], fma((double)a[t][q].x, xj[t][0], acc[q]));
+        if (J < J1 && J > I) {  // uniform over the workgroup
+            double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                c0 = fma((double)a[t][q].x, xi[q], c0);
+                c1 = fma((double)a[t][q].y, xi[q], c1);
+            }
+            c0 += __shfl_xor(c0, 32);
+            c1 += __shfl_xor(c1, 32);
+            if (lane < 32) {
+                s_col[w][c] = c0;
+                s_col[w][c + 1] = c1;
+            }
+            __syncthreads();
+            if (tid < NB)
+                Pc[((int64_t)J * nblk + I) * NB + tid] = (s_col[0][tid] + s_col[1][tid]) + (s_col[2][tid] + s_col[3][tid]);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double v = acc[q];
+        for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o);
+        acc[q] = v;
+    }
+    if ((lane & 31) == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s_row[rg + 8 * q] = acc[q];
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int ch = (J0 - I) / SYMV_CH;
+        Pr[((int64_t)I * maxch + ch) * NB + tid] = s_row[tid];
     }
 }
 
@@ -141,9 +242,15 @@ static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, co
     void *pr, *pc;
     if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * maxch * NB, &pr))) return rc;
     if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &pc))) return rc;
-    hipLaunchKernelGGL(k_symv_tiles<T>, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
-                       lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr,
-                       (double *)pc);
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_symv_tiles, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A, lda, n,
+                           nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr, (double *)pc);
+    else if (lda % 2 == 0)
+        hipLaunchKernelGGL(k_symv_tiles_f32<true>, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
+                           lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr, (double *)pc);
+    else
+        hipLaunchKernelGGL(k_symv_tiles_f32<false>, dim3((unsigned)ctx->symv_items), dim3(256), 0, ctx->stream, A,
+                           lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr, (double *)pc);
     if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
                        (const double *)pc, nblk, maxch, n, y);

@@ -72,15 +72,10 @@ __device__ int sturm_count(const double *alpha, const double *beta, int64_t m, d
 
 // theta[i] for i < nwant: the wanted eigenvalues ascending; theta[nwant]: the
 // opposite extreme (used for ||T||).
-__global__ __launch_bounds__(64) void k_tri_bisect(const double *__restrict__ alpha,
-                                                   const double *__restrict__ beta, int64_t m,
-                                                   int64_t nwant, int which, double *theta)
+__device__ double bisect_index(const double *__restrict__ alpha, const double *__restrict__ beta, int64_t m,
+                               int64_t idx)
 {
     const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    int64_t idx;
-    if (i < nwant) idx = (which == 0) ? i : m - nwant + i;
-    else idx = (which == 0) ? m - 1 : 0;
     double gl, gu, pivmin;
     gershgorin(alpha, beta, m, &gl, &gu, &pivmin);
     const double tn = fmax(fabs(gl), fabs(gu));
@@ -101,7 +96,37 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double *__restrict__ al
             hi = nhi;
         }
     }
-    if (lane == 0) theta[i] = 0.5 * (lo + hi);
+    return 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(64) void k_tri_bisect(const double *__restrict__ alpha,
+                                                   const double *__restrict__ beta, int64_t m,
+                                                   int64_t nwant, int which, double *theta)
+{
+    const int64_t i = blockIdx.x;
+    int64_t idx;
+    if (i < nwant) idx = (which == 0) ? i : m - nwant + i;
+    else idx = (which == 0) ? m - 1 : 0;
+    const double v = bisect_index(alpha, beta, m, idx);
+    if (threadIdx.x == 0) theta[i] = v;
+}
+
+// Eigenvalues of T with ascending indices first .. first+count-1 into
+// theta[0..count); theta[count] = the largest (which = 0) or smallest
+// (which = 1) eigenvalue, theta[count+1] = the other extreme -- the ends
+// that bound ||T||.
+__global__ __launch_bounds__(64) void k_tri_bisect_range(const double *__restrict__ alpha,
+                                                         const double *__restrict__ beta, int64_t m,
+                                                         int64_t first, int64_t count, int which,
+                                                         double *theta)
+{
+    const int64_t i = blockIdx.x;
+    int64_t idx;
+    if (i < count) idx = first + i;
+    else if (i == count) idx = (which == 0) ? m - 1 : 0;
+    else idx = (which == 0) ? 0 : m - 1;
+    const double v = bisect_index(alpha, beta, m, idx);
+    if (threadIdx.x == 0) theta[i] = v;
 }
 
 // LU of T - lam I with partial pivoting; factors go to f (5 arrays of m):
@@ -320,9 +345,10 @@ __global__ __launch_bounds__(256) void k_tri_cluster(int64_t m, int64_t nwant,
 // ||T|| ~ max |theta| over the nwant computed values and the opposite extreme
 __global__ __launch_bounds__(64) void k_conv_count(const double *theta, const double *lastcomp,
                                                    const double *beta_m, int64_t nwant, int64_t i0,
-                                                   int64_t cnt, double tol, int *nconv)
+                                                   int64_t cnt, int tn_extra, double tol, int *nconv)
 {
-    const double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
+    double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
+    if (tn_extra) tn = fmax(tn, fabs(theta[nwant + 1]));
     const double bm = fabs(*beta_m);
     int c = 0;
     for (int64_t i = i0 + threadIdx.x; i < i0 + cnt; i += 64) c += (bm * lastcomp[i] <= tol * tn);
@@ -339,6 +365,14 @@ int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_
 {
     hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)(nwant + 1)), dim3(64), 0, st, alpha, beta, m,
                        nwant, which, theta);
+    return ok();
+}
+
+int launch_tri_bisect_range(const double *alpha, const double *beta, int64_t m, int64_t first,
+                            int64_t count, int which, double *theta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tri_bisect_range, dim3((unsigned)(count + 2)), dim3(64), 0, st, alpha, beta, m, first,
+                       count, which, theta);
     return ok();
 }
 
@@ -360,9 +394,10 @@ int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64
 }
 
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
-                      int64_t nwant, int64_t i0, int64_t cnt, double tol, int *nconv, hipStream_t st)
+                      int64_t nwant, int64_t i0, int64_t cnt, int tn_extra, double tol, int *nconv,
+                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, i0, cnt, tol,
-                       nconv);
+    hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, i0, cnt,
+                       tn_extra, tol, nconv);
     return ok();
 }

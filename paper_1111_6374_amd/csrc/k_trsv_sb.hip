@@ -113,15 +113,31 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_n(const T *__restrict__ U, int
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             nr[c][r] = has_next ? N[(int64_t)S * SBR * SBR + (int64_t)(rowl + r) * SBR + c * NB + l] : 0.0;
-    // Y rows: Uinv_SS[rowl + r][k] r'_S[k], k >= rowl (upper triangle), k = c*64 + l
+    // Y rows: Uinv_SS[rowl + r][k] r'_S[k], k >= rowl (upper triangle), k = c*64 + l.
+    // All r' polls are issued together and settled before any product, so
+    // the exchange costs one round trip and the Uinv loads pipeline.
     double y[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = loc; c < TPS; ++c) {
-        const int64_t kk = s0 + (int64_t)c * NB + l;
-        if (kk >= n) break;  // lanes past n stop; U^-1 rows beyond n are zero
-        const double rv = settle(ld_bits(rstage + kk), rstage + kk, &ctl->err);
+    {
+        unsigned long long rb[TPS];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            y[r] = fma(Uinv[(int64_t)S * SBR * SBR + (int64_t)(rowl + r) * SBR + c * NB + l], rv, y[r]);
+        for (int c = 0; c < TPS; ++c) {
+            const int64_t kk = s0 + (int64_t)c * NB + l;
+            rb[c] = ld_bits(rstage + (kk < n ? kk : n - 1));
+        }
+        double rv[TPS];
+#pragma unroll
+        for (int c = 0; c < TPS; ++c) {
+            const int64_t kk = s0 + (int64_t)c * NB + l;
+            // entries past n stay 0 (U^-1 rows beyond n are zero)
+            rv[c] = (c >= loc && kk < n) ? settle(rb[c], rstage + kk, &ctl->err) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < TPS; ++c) {
+            if (c < loc) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                y[r] = fma(Uinv[(int64_t)S * SBR * SBR + (int64_t)(rowl + r) * SBR + c * NB + l], rv[c], y[r]);
+        }
     }
     // the link: x_{S+1} arrives; y - N_S x_{S+1} is folded into one wave sum
     if (has_next) {
@@ -234,16 +250,29 @@ __global__ __launch_bounds__(1024) void k_trsv_sb_t(const T *__restrict__ U, int
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             nr[c][r] = has_prev ? Nt[(int64_t)S * SBR * SBR + (int64_t)(al + r) * SBR + c * NB + l] : 0.0;
-    // Y' entries: Uinv_SS^T[al + r][k] r'_S[k], k <= al + r, k = c*64 + l
+    // Y' entries: Uinv_SS^T[al + r][k] r'_S[k], k <= al + r, k = c*64 + l;
+    // all r' polls in flight together, then the products
     double y[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c <= loc; ++c) {
-        const int64_t kk = s0 + (int64_t)c * NB + l;
-        const int64_t kc = kk < n ? kk : n - 1;
-        const double rv = settle(ld_bits(rstage + kc), rstage + kc, &ctl->err);
-        const double rr = (kk < n) ? rv : 0.0;
+    {
+        unsigned long long rb[TPS];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            y[r] = fma(UinvT[(int64_t)S * SBR * SBR + (int64_t)(al + r) * SBR + c * NB + l], rr, y[r]);
+        for (int c = 0; c < TPS; ++c) {
+            const int64_t kk = s0 + (int64_t)c * NB + l;
+            rb[c] = ld_bits(rstage + (kk < n ? kk : n - 1));
+        }
+        double rv[TPS];
+#pragma unroll
+        for (int c = 0; c < TPS; ++c) {
+            const int64_t kk = s0 + (int64_t)c * NB + l;
+            rv[c] = (c <= loc && kk < n) ? settle(rb[c], rstage + kk, &ctl->err) : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < TPS; ++c) {
+            if (c > loc) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                y[r] = fma(UinvT[(int64_t)S * SBR * SBR + (int64_t)(al + r) * SBR + c * NB + l], rv[c], y[r]);
+        }
     }
     // the link: x_{S-1} (a complete super-block) arrives
     if (has_prev) {
