@@ -33,6 +33,27 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, n, prec):
+    """HBM bytes per launch of `kernel` from a committed counter summary under
+    profiles/ (two calibrated rocprofv3 --pmc passes), or None when there is
+    none for this size or the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    import re
+
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for m in re.finditer(r"<!-- traffic (.*?) -->", open(f).read()):
+            kv = dict(item.split("=", 1) for item in m.group(1).split())
+            if kv.get("kernel") != kernel or int(kv.get("n", -1)) != n or kv.get("prec") != prec:
+                continue
+            h = hashlib.sha256()
+            for src in kv["sources"].split(","):
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            if h.hexdigest()[:16] == kv.get("sha256_16"):
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(n_target, law="spaced"):
     """The oracle (plain C, FP64) on a bounded sample: a full solve at n = 2048
     of the same generator, scaled by (n_target / 2048)^3 (every stage is O(n^3))."""
@@ -64,6 +85,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (exploration; the config label then says so)")
     ap.add_argument("--s", type=int, default=0, help="override s")
     ap.add_argument("--no-fp64-compare", action="store_true", help="--config 2: skip the FP64 solve")
+    ap.add_argument("--trsv-only", action="store_true",
+                    help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
+                         "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -79,6 +103,8 @@ def main():
     import paper_1111_6374_amd as gs
 
     cfg = dict(CONFIGS[args.config])
+    if args.trsv_only:
+        return trsv_only(args, cfg)
     if args.n or args.s:
         cfg["n"] = args.n or cfg["n"]
         cfg["s"] = args.s or cfg["s"]
@@ -160,8 +186,9 @@ def main():
         "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "fp64",
                    "block": 1, "lanczos_steps": int(last.steps), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None, "traffic": None,
-                     "kernel": "k_trsv_n/k_trsv_t (KI1/KI3)", "avg_launch_ms": trsv_ms,
+                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
+                     "traffic": measured_traffic("k_trsv_sb", n, "fp64"),
+                     "kernel": "k_trsv_sb_n/k_trsv_sb_t (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
                      "algorithmic_bytes_per_launch": tri_bytes + vec_bytes},
         "kernels": {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
                     "samples": samples},
@@ -175,6 +202,34 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
+
+
+def trsv_only(args, cfg):
+    """KI1 and KI3 alone (no eigen-solve, no QR): the workload of the byte-
+    counter passes.  Also one device copy of n^2 FP64 values, whose read and
+    written bytes are known exactly, to calibrate the counters."""
+    import torch
+
+    import paper_1111_6374_amd as gs
+
+    n = args.n or cfg["n"]
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(6374)
+    U = torch.triu(torch.randn(n, n, generator=g, device=dev, dtype=torch.float64) / math.sqrt(n), 1)
+    U.diagonal().copy_(1.0 + torch.rand(n, generator=g, device=dev, dtype=torch.float64))
+    b = torch.randn(n, generator=g, device=dev, dtype=torch.float64)
+    x = torch.empty_like(b)
+    C = torch.empty_like(U)
+    with gs.Solver() as sv:
+        for trans in (0, 1):
+            for _ in range(max(1, args.steps)):
+                rc = gs.gsyeig_trsv(sv.ctx, n, U, n, trans, b, x)
+                if rc:
+                    raise gs.GsyeigError("gsyeig_trsv", rc)
+        C.copy_(U)  # reads and writes 8 n^2 bytes
+        torch.cuda.synchronize()
+    log(f"trsv-only n={n}: {2 * max(1, args.steps)} solves and one copy of {8 * n * n} bytes done")
 
 
 def bench_mixed(args, cfg):
@@ -265,8 +320,9 @@ def bench_mixed(args, cfg):
                    "block": 1, "lanczos_steps": int(last.steps), "refine_rounds": int(last.refine_iters),
                    "block_cols": int(last.block_cols), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None, "traffic": None,
-                     "kernel": "k_trsv_sb_n/k_trsv_sb_t on FP32 U (KI1/KI3)", "avg_launch_ms": trsv_ms,
+                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
+                     "traffic": measured_traffic("k_trsv_sb", n, "fp32"),
+                     "kernel": "k_trsv_sb_n/k_trsv_sb_t on FP32 U (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
                      "algorithmic_bytes_per_launch": tri32 + vec},
         "kernels": {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
                     "samples": samples},

@@ -370,6 +370,14 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     const int64_t every = std::max<int64_t>(1, o->check_every);
     int64_t m = 0, nconv = 0;
     bool checked_at_m = false;
+    // check schedule: every `every` steps near convergence; further apart
+    // (up to 4x) while the slowest innermost wanted pair is predicted to
+    // need many more steps (its residual ratio extrapolated linearly in
+    // log scale from the last two pre-checks)
+    int64_t next_check = every;
+    int64_t prev_m = -1;
+    double prev_rho = 0.0;
+    double *ratio_d = (double *)ctx->dscal + 32;
     ctx->npev = 0;
     ctx->prof_samples = 0;
     ctx->prof_ms[0] = ctx->prof_ms[1] = ctx->prof_ms[2] = 0.0;
@@ -379,16 +387,38 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
         TRY(lz_step(ctx, n, op, V, ldv, alpha, beta, k, b, sample));
         m = k + 1;
         checked_at_m = false;
-        if (m >= nvec && (m % every == 0 || m == mmax)) {
-            if (q < s && m < mmax) {
-                const int64_t first = o->which ? m - s : s - q;
-                TRY(launch_tri_bisect_range(alpha, beta, m, first, q, o->which, theta_q, ctx->stream));
-                TRY(launch_tri_vectors(alpha, beta, m, q, theta_q, nullptr, 0, tri, 0, lastc_q, ctx->stream));
-                TRY(launch_conv_count(theta_q, lastc_q, beta + (m - 1), q, 0, q, 1, o->tol, nconv_d, ctx->stream));
+        if (m >= nvec && (m >= next_check || m == mmax)) {
+            next_check = m + every;
+            if (m < mmax) {
+                const int64_t qq = std::min<int64_t>(q, s);
+                const int64_t first = o->which ? m - s : s - qq;
+                TRY(launch_tri_bisect_range(alpha, beta, m, first, qq, o->which, theta_q, ctx->stream));
+                TRY(launch_tri_vectors(alpha, beta, m, qq, theta_q, nullptr, 0, tri, 0, lastc_q, ctx->stream));
+                TRY(launch_conv_count(theta_q, lastc_q, beta + (m - 1), qq, 0, qq, 1, o->tol, nconv_d, ctx->stream,
+                                      ratio_d));
                 HIP_TRY(hipMemcpyAsync(nconv_h, nconv_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIP_TRY(hipMemcpyAsync((double *)ctx->host_pinned + 8, ratio_d, sizeof(double),
+                                       hipMemcpyDeviceToHost, ctx->stream));
                 HIP_TRY(hipStreamSynchronize(ctx->stream));
                 TRY(prof_harvest(ctx));
-                if (*nconv_h < q) continue;
+                const double ratio = ((double *)ctx->host_pinned)[8];
+                if (*nconv_h < qq) {
+                    const double rho = log10(std::max(ratio, 1.0));
+                    int64_t interval = 2 * every;
+                    if (prev_m >= 0 && prev_rho > rho) {
+                        const double remaining = rho * (double)(m - prev_m) / (prev_rho - rho);
+                        interval = std::min<int64_t>(4 * every, std::max<int64_t>(every, (int64_t)(0.6 * remaining)));
+                    }
+                    prev_m = m;
+                    prev_rho = rho;
+                    next_check = m + interval;
+                    continue;
+                }
+                if (qq == s) {  // the pre-check covered every wanted pair
+                    nconv = s;
+                    checked_at_m = false;
+                    break;
+                }
             }
             TRY(launch_tri_bisect(alpha, beta, m, nvec, o->which, theta, ctx->stream));
             TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, nullptr, 0, tri, 0, lastc, ctx->stream));

@@ -186,7 +186,7 @@ int launch_tri_bisect_range(const double *alpha, const double *beta, int64_t m, 
 // tn_extra = 1: theta[nwant + 1] also enters the ||T|| estimate
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
                       int64_t nwant, int64_t i0, int64_t cnt, int tn_extra, double tol, int *nconv,
-                      hipStream_t st);
+                      hipStream_t st, double *maxratio = nullptr);
 
 // mixed-precision refinement (k_refine.hip)
 struct RefineOp {          // the FP32 operator C~ = U~^-T A~ U~^-1

@@ -343,17 +343,30 @@ __global__ __launch_bounds__(256) void k_tri_cluster(int64_t m, int64_t nwant,
 
 // nconv = #{ i in [i0, i0 + cnt) : |beta_m| lastcomp[i] <= tol ||T|| },
 // ||T|| ~ max |theta| over the nwant computed values and the opposite extreme
+// Optionally *maxratio = max_i |beta_m| lastcomp[i] / (tol ||T||) over the
+// same range (the distance to convergence of the slowest pair).
 __global__ __launch_bounds__(64) void k_conv_count(const double *theta, const double *lastcomp,
                                                    const double *beta_m, int64_t nwant, int64_t i0,
-                                                   int64_t cnt, int tn_extra, double tol, int *nconv)
+                                                   int64_t cnt, int tn_extra, double tol, int *nconv,
+                                                   double *maxratio)
 {
     double tn = fmax(fmax(fabs(theta[0]), fabs(theta[nwant - 1])), fabs(theta[nwant]));
     if (tn_extra) tn = fmax(tn, fabs(theta[nwant + 1]));
     const double bm = fabs(*beta_m);
     int c = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i0 + cnt; i += 64) c += (bm * lastcomp[i] <= tol * tn);
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (threadIdx.x == 0) *nconv = c;
+    double mr = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i0 + cnt; i += 64) {
+        c += (bm * lastcomp[i] <= tol * tn);
+        mr = fmax(mr, bm * lastcomp[i] / fmax(tol * tn, 0x1p-1000));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o);
+        mr = fmax(mr, __shfl_xor(mr, o));
+    }
+    if (threadIdx.x == 0) {
+        *nconv = c;
+        if (maxratio) *maxratio = mr;
+    }
 }
 
 inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
@@ -395,9 +408,9 @@ int launch_tri_vectors(const double *alpha, const double *beta, int64_t m, int64
 
 int launch_conv_count(const double *theta, const double *lastcomp, const double *beta_m,
                       int64_t nwant, int64_t i0, int64_t cnt, int tn_extra, double tol, int *nconv,
-                      hipStream_t st)
+                      hipStream_t st, double *maxratio)
 {
     hipLaunchKernelGGL(k_conv_count, dim3(1), dim3(64), 0, st, theta, lastcomp, beta_m, nwant, i0, cnt,
-                       tn_extra, tol, nconv);
+                       tn_extra, tol, nconv, maxratio);
     return ok();
 }
