@@ -69,7 +69,9 @@ typedef struct {
                            /*   Rayleigh-Ritz refinement on the original (A, B)   */
     int block;             /* Lanczos block size; 1 = single-vector Lanczos       */
     int which;             /* 0 = s smallest (default), 1 = s largest             */
-    int invert;            /* reserved (0): solve the inverse pencil (B, A)       */
+    int invert;            /* 1: A must be SPD; solve the inverse pencil (B, A)  */
+                           /*   for mu = 1/lambda (Sec. 3.1's MD run), return    */
+                           /*   the pairs of (A, B) (gsyeig_solve only)           */
     double tol;            /* Ritz-residual tolerance relative to ||T_m||          */
                            /*   (default 1e-12); Section 3.3 used tol = 0, i.e.   */
                            /*   machine precision, in ARPACK's dsaupd             */
@@ -87,6 +89,13 @@ typedef struct {
     int64_t refine_inner;  /* MINRES steps per correction round (default 20)      */
     int64_t guard;         /* extra Ritz vectors carried through the refinement   */
                            /*   (0 = max(8, ceil(s/4)))                           */
+    /* both modes */
+    int64_t reorth;        /* full re-orthogonalisation against all of V_k, by   */
+                           /*   classical Gram-Schmidt: 0 = two passes every step */
+                           /*   (Sec. 2.3, after Kahan); 1 (default) = the second */
+                           /*   pass only when the first kept less than 1/sqrt(2) */
+                           /*   of the norm (orthogonality monitored and amended, */
+                           /*   the alternative Sec. 2.3 names)                   */
 } gsyeig_opts;
 
 typedef struct {
@@ -281,7 +290,11 @@ int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
  * FP32 trailing updates into an internal FP32 factor U~, the Lanczos sweeps
  * read FP32 copies of A and U~ (FP64 vectors, alpha/beta, re-orthogonal-
  * isation and T), s + guard Ritz vectors are back-solved with U~ and
- * refined as by gsyeig_refine; info reports both phases.  Returns
+ * refined as by gsyeig_refine; info reports both phases.
+ * opts->invert = 1 (A SPD): the pencil (B, A) is solved for its extreme
+ * mu = 1/lambda at the other end (Sec. 3.1 used this for the MD problem),
+ * then Lambda = 1/mu ascending and X rescaled to X^T B X = I; A and B are not
+ * modified (FP64 mode factors a copy of A); a non-SPD A returns +k.  Returns
  * GSYEIG_ENOCONV unless the FP32-sweep Lanczos met tol AND the refinement
  * met eta_tol.  Lambda (device, s)
  * receives the eigenvalues ascending; X (device, n x s column-major,

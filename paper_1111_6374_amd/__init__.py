@@ -54,7 +54,8 @@ class gsyeig_opts(ctypes.Structure):
                 ("invert", ctypes.c_int), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("check_every", ctypes.c_int64), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
                 ("profile_every", ctypes.c_int64), ("eta_tol", ctypes.c_double),
-                ("refine_iters", ctypes.c_int64), ("refine_inner", ctypes.c_int64), ("guard", ctypes.c_int64)]
+                ("refine_iters", ctypes.c_int64), ("refine_inner", ctypes.c_int64), ("guard", ctypes.c_int64),
+                ("reorth", ctypes.c_int64)]
 
 
 class gsyeig_info(ctypes.Structure):

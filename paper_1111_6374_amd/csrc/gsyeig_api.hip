@@ -113,6 +113,7 @@ static void opts_fill_defaults(gsyeig_opts *o)
     o->refine_iters = 10;
     o->refine_inner = 20;
     o->guard = 0;
+    o->reorth = 1;
 }
 
 // width of the mixed-mode refinement block: s wanted + guard vectors
@@ -291,7 +292,9 @@ static int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S
 }
 
 struct LzBufs {
-    double *z, *tmp, *red, *red2, *h, *normpart;
+    double *z, *tmp, *red, *red2, *h, *normpart, *z0part;
+    int *flag;       // second Gram-Schmidt pass needed (device)
+    int reorth;      // 0: always two passes; 1: second pass when needed
 };
 
 static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
@@ -301,11 +304,15 @@ static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
     b->z = (double *)p;
     TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
     b->tmp = (double *)p;
-    const size_t red = (size_t)lz_red_parts(n) * (size_t)(kmax + 8) + (size_t)lz_norm_parts(n) + 1024;
+    const size_t red = (size_t)lz_red_parts(n) * (size_t)(kmax + 8) + (size_t)lz_norm_parts(n) +
+                       (size_t)lz_z0_parts(n) + 1024 + 64;
     TRY(ws_get(ctx, WS_RED, sizeof(double) * red, &p));
     b->red = (double *)p;
     b->normpart = b->red + 1024;
-    b->red2 = b->normpart + lz_norm_parts(n);
+    b->z0part = b->normpart + lz_norm_parts(n);
+    b->flag = (int *)(b->z0part + lz_z0_parts(n));
+    b->red2 = b->z0part + lz_z0_parts(n) + 64;
+    b->reorth = 1;
     TRY(ws_get(ctx, WS_RED2, sizeof(double) * (size_t)(kmax + 8), &p));
     b->h = (double *)p;
     return 0;
@@ -318,9 +325,17 @@ static int lz_step(gsyeig_ctx *ctx, int64_t n, const LzOp &op, double *V, int64_
     const double *wk = V + k * ldv;
     const double *wp = (k > 0) ? V + (k - 1) * ldv : wk;
     TRY(apply_op(ctx, n, op, wk, b.z, b.tmp, sample));
-    TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream));
-    TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream));
-    TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream));
+    if (b.reorth) {
+        // second pass only where the first lost more than 1/sqrt(2) of the norm
+        TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream, b.z0part));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream));
+        TRY(launch_reorth_flag(b.z0part, n, b.normpart, b.flag, ctx->stream));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream, b.flag));
+    } else {
+        TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream));
+    }
     TRY(launch_lz_normalize(b.z, V + (k + 1) * ldv, beta, k, n, b.normpart, ctx->stream));
     return 0;
 }
@@ -355,6 +370,7 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     double *tri = (double *)p;
     LzBufs b;
     TRY(lz_bufs(ctx, n, mmax, &b));
+    b.reorth = o->reorth ? 1 : 0;
     TRY(ctl_reserve(ctx, n));
     int *nconv_d = (int *)ctx->dscal;
     int *nconv_h = (int *)ctx->host_pinned;
@@ -689,6 +705,61 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
 }
 
+extern "C" int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
+                            int64_t ldb, const gsyeig_opts *opts, double *Lambda, double *X, int64_t ldx,
+                            gsyeig_info *info);
+
+// The inverse pencil (Sec. 3.1 used it for the MD problem): with A SPD the
+// s smallest eigenvalues of (A, B) are the reciprocals of the s largest of
+// (B, A), which Lanczos finds quickly.  The pencil (B, A) is solved by the
+// same path (in FP64 mode A is factored from a copy, so A and B are left as
+// they are), then lambda = 1/mu, the order is reversed and x is rescaled
+// from x^T A x = 1 to x^T B x = 1; the FP64 check runs on (A, B).
+static int solve_inverted(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
+                          int64_t ldb, const gsyeig_opts &o, double *Lambda, double *X, int64_t ldx,
+                          gsyeig_info *info)
+{
+    gsyeig_opts oi = o;
+    oi.invert = 0;
+    oi.which = 1 - o.which;
+    const int64_t ldw = round_ld(n);
+    void *p;
+    double *Af = const_cast<double *>(A);
+    int64_t ldf = lda;
+    if (o.prec == GSYEIG_FP64) {  // the factor overwrites its matrix: work on a copy of A
+        TRY(ws_get(ctx, WS_ACOPY, sizeof(double) * (size_t)ldw * (size_t)n, &p));
+        Af = (double *)p;
+        ldf = ldw;
+        TRY(launch_blk_copy(A, lda, Af, ldf, n, n, ctx->stream));
+    }
+    TRY(ws_get(ctx, WS_INV, sizeof(double) * ((size_t)ldw * (size_t)s + (size_t)s + 64), &p));
+    double *Xi = (double *)p, *mu = Xi + ldw * s;
+    gsyeig_info inf;
+    memset(&inf, 0, sizeof(inf));
+    const int rc = gsyeig_solve(ctx, n, s, B, ldb, Af, ldf, &oi, mu, Xi, ldw, &inf);
+    if (rc != 0 && rc != GSYEIG_ENOCONV) return rc;
+    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
+    TRY(launch_invert_pairs(mu, Xi, ldw, Lambda, X, ldx, n, s, ctx->stream));
+    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
+    double *res_d = (double *)ctx->dscal + 64;
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, nullptr, Lambda, X, ldx, res_d));
+    HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
+    double *h = (double *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    inf.eta_max = h[0];
+    inf.rho_f = h[1];
+    inf.omega = h[2];
+    inf.normA_f = h[3];
+    inf.normB_f = h[4];
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5]));
+    inf.t_check_ms += t;
+    inf.t_total_ms += t;
+    if (info) *info = inf;
+    return rc;
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -776,6 +847,10 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     b += trsv_sb_bytes(n);                                        // super-block solve data
     b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
     b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
+    if (o.invert) {
+        b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
+        if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
+    }
     if (o.prec == GSYEIG_MIXED) {
         const int64_t k = mixed_block(n, s, &o);
         b += 2 * sizeof(float) * (size_t)ldv * (size_t)n;           // A~, U~ (FP32)
@@ -879,6 +954,7 @@ int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, i
     TRY(lz_bufs(ctx, n, k, &b));
     TRY(launch_normalize_into(v0, V, n, b.red, nullptr, ctx->stream));
     const LzOp op = op_fp64(A, lda, U, ldu, Dinv);
+    b.reorth = 0;  // this entry point always applies both Gram-Schmidt passes
     for (int64_t j = 0; j < k; ++j) TRY(lz_step(ctx, n, op, V, ldv, alpha, beta, j, b));
     return 0;
 }
@@ -986,12 +1062,13 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (ldb < n) return -7;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
-    if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block != 1 || o.invert ||
+    if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block != 1 || (o.invert != 0 && o.invert != 1) ||
         (o.which != 0 && o.which != 1))
         return -8;
     if (!Lambda) return -9;
     if (!X) return -10;
     if (ldx < n) return -11;
+    if (o.invert) return solve_inverted(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
     if (o.prec == GSYEIG_MIXED) return solve_mixed(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
 
     gsyeig_info inf;

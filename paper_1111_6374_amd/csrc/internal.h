@@ -59,6 +59,8 @@ enum WsSlot {
     WS_U32,        // FP32 Cholesky factor (mixed mode)
     WS_REFINE,     // blocks and small matrices of the FP64 refinement
     WS_RITZ,       // orthonormalisation of the Ritz coefficient matrix
+    WS_ACOPY,      // working copy of A factored by the inverse-pencil solve (FP64 mode)
+    WS_INV,        // mu and vectors of the inverse-pencil solve
     WS_COUNT
 };
 
@@ -168,10 +170,16 @@ int launch_fill_splitmix(double *v, int64_t n, uint64_t seed, hipStream_t st);
 int launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);
 int launch_normalize_into(const double *v, double *w, int64_t n, double *part, double *norm_out,
                           hipStream_t st);
+// z0part (optional, lz_z0_parts(n) entries): partial sums of the projected z^2
 int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *alpha,
-                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st);
+                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st,
+                    double *z0part = nullptr);
+// run (optional device flag): the pass does nothing when *run == 0
 int launch_cgs_pass(const double *V, int64_t ldv, int64_t n, int64_t kcols, double *z, double *part,
-                    double *h, double *normpart, hipStream_t st);
+                    double *h, double *normpart, hipStream_t st, const int *run = nullptr);
+int lz_z0_parts(int64_t n);
+// *flag = 1 if the first pass shrank z below 1/sqrt(2) of its norm
+int launch_reorth_flag(const double *z0part, int64_t n, const double *z1part, int *flag, hipStream_t st);
 int launch_lz_normalize(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
                         const double *normpart, hipStream_t st);
 
@@ -212,7 +220,9 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
                        int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st);
 int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
                     hipStream_t st);
-int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st);   // r x r identity, column-major
+int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st);
+int launch_invert_pairs(const double *mu, const double *Xin, int64_t ldi, double *lam, double *Xout,
+                        int64_t ldo, int64_t n, int64_t s, hipStream_t st);   // r x r identity, column-major
 int launch_accum_info(const int *src, int *dst, hipStream_t st);        // *dst = *src if *dst == 0
 int launch_flag_offdiag(const double *G, int64_t r, double thresh, int *flag, hipStream_t st);
 size_t syev_small_scratch(int64_t N, int64_t nwant);

@@ -118,13 +118,34 @@ __global__ __launch_bounds__(256) void k_lz_three_term(double *z, const double *
 
 // alpha_k = sum(part); z := z - alpha_k w_k
 __global__ __launch_bounds__(256) void k_lz_sub_alpha(double *z, const double *wk, double *alpha,
-                                                      int64_t k, int64_t n, const double *part, int P)
+                                                      int64_t k, int64_t n, const double *part, int P,
+                                                      double *z0part)
 {
     __shared__ double sbuf[4];
     const double a = sum_parts(part, P, sbuf);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) z[i] = fma(-a, wk[i], z[i]);
+    double zz = 0.0;
+    if (i < n) {
+        zz = fma(-a, wk[i], z[i]);
+        z[i] = zz;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) alpha[k] = a;
+    if (z0part) {
+        const double t = block_sum(zz * zz, sbuf);
+        if (threadIdx.x == 0) z0part[blockIdx.x] = t;
+    }
+}
+
+// Second Gram-Schmidt pass needed?  (Kahan's test as used by Parlett: a
+// pass that keeps at least 1/sqrt(2) of the norm leaves z orthogonal to V to
+// working accuracy.)  flag = 1 if ||z1||^2 < ||z0||^2 / 2.
+__global__ __launch_bounds__(256) void k_reorth_flag(const double *z0part, int P0, const double *z1part, int P1,
+                                                     int *flag)
+{
+    __shared__ double sbuf[4];
+    const double a = sum_parts(z0part, P0, sbuf);
+    const double b = sum_parts(z1part, P1, sbuf);
+    if (threadIdx.x == 0) *flag = (b < 0.5 * a) ? 1 : 0;
 }
 
 // Gram-Schmidt projection, stage 1: part[rc * kcols + c] = V(rows of rc, c)^T z(rows of rc)
@@ -132,8 +153,9 @@ __global__ __launch_bounds__(256) void k_lz_sub_alpha(double *z, const double *w
 __global__ __launch_bounds__(256) void k_gemv_t_parts(const double *__restrict__ V, int64_t ldv,
                                                       int64_t n, int64_t kcols,
                                                       const double *__restrict__ z,
-                                                      double *__restrict__ part)
+                                                      double *__restrict__ part, const int *run)
 {
+    if (run && *run == 0) return;
     __shared__ double sred[4][8];
     const int64_t c0 = (int64_t)blockIdx.x * 8;
     const int rc = blockIdx.y;
@@ -170,8 +192,9 @@ __global__ __launch_bounds__(256) void k_gemv_t_parts(const double *__restrict__
 }
 
 // stage 2: h[c] = sum over row chunks
-__global__ void k_gemv_t_reduce(const double *part, int RC, int64_t kcols, double *h)
+__global__ void k_gemv_t_reduce(const double *part, int RC, int64_t kcols, double *h, const int *run)
 {
+    if (run && *run == 0) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= kcols) return;
     double s = 0.0;
@@ -185,8 +208,9 @@ __global__ __launch_bounds__(512) void k_gemv_n_update(const double *__restrict_
                                                        int64_t n, int64_t kcols,
                                                        const double *__restrict__ h,
                                                        double *__restrict__ z,
-                                                       double *__restrict__ normpart)
+                                                       double *__restrict__ normpart, const int *run)
 {
+    if (run && *run == 0) return;
     __shared__ double s[8][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * 64 + lane;
@@ -264,28 +288,37 @@ int launch_normalize_into(const double *v, double *w, int64_t n, double *part, d
 }
 
 int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *alpha,
-                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st)
+                    const double *beta, int64_t k, int64_t n, double *part, hipStream_t st, double *z0part)
 {
     const int P = lz_red_parts(n);
     hipLaunchKernelGGL(k_lz_three_term, dim3(P), dim3(256), 0, st, z, wprev, wk, beta, k, n, part);
     if (ok()) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_lz_sub_alpha, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wk, alpha,
-                       k, n, (const double *)part, P);
+                       k, n, (const double *)part, P, z0part);
     return ok();
 }
 
 int launch_cgs_pass(const double *V, int64_t ldv, int64_t n, int64_t kcols, double *z, double *part,
-                    double *h, double *normpart, hipStream_t st)
+                    double *h, double *normpart, hipStream_t st, const int *run)
 {
     const int RC = lz_red_parts(n);
     hipLaunchKernelGGL(k_gemv_t_parts, dim3((unsigned)cdiv(kcols, 8), RC), dim3(256), 0, st, V, ldv,
-                       n, kcols, (const double *)z, part);
+                       n, kcols, (const double *)z, part, run);
     if (ok()) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_gemv_t_reduce, dim3((unsigned)cdiv(kcols, 256)), dim3(256), 0, st,
-                       (const double *)part, RC, kcols, h);
+                       (const double *)part, RC, kcols, h, run);
     if (ok()) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_gemv_n_update, dim3((unsigned)cdiv(n, 64)), dim3(512), 0, st, V, ldv, n,
-                       kcols, (const double *)h, z, normpart);
+                       kcols, (const double *)h, z, normpart, run);
+    return ok();
+}
+
+int lz_z0_parts(int64_t n) { return (int)cdiv(n, 256); }
+
+int launch_reorth_flag(const double *z0part, int64_t n, const double *z1part, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(256), 0, st, z0part, lz_z0_parts(n), z1part, lz_norm_parts(n),
+                       flag);
     return ok();
 }
 

@@ -278,6 +278,20 @@ __global__ void k_accum_info(const int *src, int *dst)
     if (threadIdx.x == 0 && blockIdx.x == 0 && *src != 0 && *dst == 0) *dst = *src;
 }
 
+// Pairs (mu_i, x_i) of the inverse pencil, mu ascending, x_i^T A x_i = 1 ->
+// pairs of (A, B): lambda_i = 1 / mu_{s-1-i} (ascending when all mu > 0),
+// x_i scaled by sqrt(|lambda_i|) so that x_i^T B x_i = 1.
+__global__ void k_invert_pairs(const double *mu, const double *Xin, int64_t ldi, double *lam, double *Xout,
+                               int64_t ldo, int64_t n, int64_t s)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    const double m = mu[s - 1 - c];
+    const double l = 1.0 / m;
+    if (i == 0) lam[c] = l;
+    if (i < n) Xout[c * ldo + i] = sqrt(fabs(l)) * Xin[(s - 1 - c) * ldi + i];
+}
+
 // ||A||_F from the row partials of k_fro_parts
 __global__ void k_sum_sqrt(const double *part, int np, double *out)
 {
@@ -501,6 +515,13 @@ int gemm_mat(const void *M, int64_t ldm, int m_f32, int f32, const double *X, in
 }  // namespace
 
 // --------------------------------------------------------------- exported
+
+int launch_invert_pairs(const double *mu, const double *Xin, int64_t ldi, double *lam, double *Xout,
+                        int64_t ldo, int64_t n, int64_t s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_invert_pairs, blk_grid(n, s), dim3(256), 0, st, mu, Xin, ldi, lam, Xout, ldo, n, s);
+    return ok();
+}
 
 int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st)
 {

@@ -348,3 +348,60 @@ def test_mixed_batched_equals_single(gs, torch):
             torch.cuda.synchronize()
             assert torch.equal(lam1, Lam[i]) and torch.equal(X1, X[i]), i
             assert infos[i].eta_max <= 1e-10
+
+
+# ------------------------------------------------------ inverse pencil (A SPD)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_inverse_pencil_fem_closed_form(gs, ctx, torch, prec):
+    """FEM stiffness/mass pair: the s smallest eigenvalues through (B, A)
+    equal the closed form; X is B-orthonormal and matches the sine modes."""
+    n, s = 900, 8
+    K, M = gen.fem_pencil(n)
+    lam_ref, X_ref = gen.fem_eigs(n, s)
+    say("invert fem", n, s, prec)
+    o = gs.gsyeig_opts_default()
+    o.prec = prec
+    o.invert = 1
+    Kd, Md = dev(torch, K), dev(torch, M)
+    Lam = torch.zeros(s, dtype=torch.float64, device="cuda")
+    Xd = torch.zeros(s, n, dtype=torch.float64, device="cuda")
+    rc, info = gs.gsyeig_solve(ctx, n, s, Kd, n, Md, n, o, Lam, Xd, n)
+    assert rc == 0, (rc, info.as_dict())
+    assert np.array_equal(host(Kd), K) and np.array_equal(host(Md), M)
+    lam, X = host(Lam), host(Xd)
+    # closed form to the FP64 normwise bound (the tests of the oracle use the same)
+    assert np.max(np.abs(lam - lam_ref) / lam_ref) <= 1e-9
+    assert info.eta_max <= 1e-10 and info.omega <= 1e-10
+    for i in range(s):  # sine modes: compare up to sign (ties in magnitude)
+        sgn = np.sign(X[i] @ X_ref[i])
+        assert np.max(np.abs(sgn * X[i] - X_ref[i])) <= 1e-6 * np.max(np.abs(X_ref[i]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_inverse_pencil_matches_direct(gs, ctx, torch, orc, prec):
+    n, s = 800, 12
+    d = gen.known_spectrum(n, "clustered", seed=gen.BASE_SEED, stream=(45, prec))  # lambda > 0: A SPD
+    say("invert known", n, s, prec)
+    o = gs.gsyeig_opts_default()
+    o.prec = prec
+    o.invert = 1
+    Lam = torch.zeros(s, dtype=torch.float64, device="cuda")
+    Xd = torch.zeros(s, n, dtype=torch.float64, device="cuda")
+    rc, info = gs.gsyeig_solve(ctx, n, s, dev(torch, d["A"]), n, dev(torch, d["B"]), n, o, Lam, Xd, n)
+    assert rc == 0, (rc, info.as_dict())
+    lam = host(Lam)
+    mx = np.abs(d["lam"]).max()
+    assert np.max(np.abs(lam - np.sort(d["lam"])[:s])) <= 1e-10 * mx
+    m = orc.metrics(d["A"], d["B"], lam, host(Xd))
+    assert m["eta_max"] <= 1e-10 and m["omega"] <= 1e-10
+
+
+def test_inverse_pencil_rejects_indefinite_a(gs, ctx, torch):
+    n, s = 200, 4
+    d = gen.known_spectrum(n, "spaced", seed=gen.BASE_SEED, stream=(46,))  # lambda in [-1, 1]: A indefinite
+    o = gs.gsyeig_opts_default()
+    o.invert = 1
+    Lam = torch.zeros(s, dtype=torch.float64, device="cuda")
+    Xd = torch.zeros(s, n, dtype=torch.float64, device="cuda")
+    rc, _ = gs.gsyeig_solve(ctx, n, s, dev(torch, d["A"]), n, dev(torch, d["B"]), n, o, Lam, Xd, n)
+    assert 1 <= rc <= n

@@ -196,3 +196,22 @@ def test_lanczos_entry_seed_equals_explicit_start(torch, gs, orc):
     assert out[0][1] == out[1][1]
     assert np.array_equal(out[0][0], out[1][0])
     assert np.max(np.abs(out[0][0] - np.sort(d["lam"])[:s])) <= 1e-12
+
+
+@pytest.mark.parametrize("law", ["spaced", "clustered"])
+def test_conditional_second_pass_matches_always_twice(torch, solver, law):
+    """Re-orthogonalisation with the second pass only when needed gives the
+    same pairs as two passes every step (both within the FP64 bar)."""
+    n, s = 1500, 30
+    d = gen.known_spectrum(n, law, seed=gen.BASE_SEED, stream=(47, n))
+    res = {}
+    for reorth in (0, 1):
+        print("[gpu-case] reorth", law, reorth, flush=True)
+        sys.stdout.flush()
+        lam, X, info = run(torch, solver, d["A"], d["B"], s, reorth=reorth)
+        assert info["rc"] == 0
+        assert info["eta_max"] <= 1e-12 and info["omega"] <= 1e-10
+        res[reorth] = lam
+    mx = np.abs(d["lam"]).max()
+    assert np.max(np.abs(res[0] - res[1])) <= 1e-12 * mx
+    assert np.max(np.abs(res[1] - np.sort(d["lam"])[:s])) <= 1e-12 * mx
