@@ -140,15 +140,17 @@ static const double *aux_m(const double *Dinv, int64_t n) { return Dinv + cdiv(n
 
 static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv);
 
-// Side data of the factor for the solves: M blocks always, super-block data
-// when the context uses super-block solves.
+// Side data of the factor for the solves: M blocks always; for the
+// super-block solves the super-block inverses, the link blocks and
+// W = blockdiag(U_SS)^-1 U_offdiag (WS_SB, WS_W).
 static int prepare_solves(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double *Dinv)
 {
     TRY(launch_make_m(U, ldu, n, Dinv, Dinv + cdiv(n, NB) * NB * NB, ctx->stream));
     if (ctx->trsv_block == 64) return 0;
-    void *p;
-    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
-    return launch_make_sb(U, ldu, n, Dinv, (double *)p, ctx->stream);
+    void *p, *q;
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
+    TRY(ws_get(ctx, WS_W, sizeof(double) * (size_t)round_ld(n) * (size_t)n, &q));
+    return launch_make_w(U, ldu, n, Dinv, (double *)p, (double *)q, round_ld(n), ctx->stream);
 }
 
 static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, double **Dinv)
@@ -165,8 +167,14 @@ static int solve_n(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, con
 {
     if (ctx->trsv_block == 64)
         return launch_trsv_n(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_n, ctx->stream);
-    return launch_trsv_sb_n(U, ldu, n, (const double *)ctx->ws[WS_SB], b, x,
-                            ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n, ctx->stream);
+    if (b == x) {  // each tile reads b across its super-block: solve from a copy
+        void *p;
+        TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
+        TRY(launch_copy(b, (double *)p, n, ctx->stream));
+        b = (const double *)p;
+    }
+    return launch_trsv_w_n((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], b, x,
+                           ctx->ctl_n, ctx->stream);
 }
 
 static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
@@ -174,8 +182,8 @@ static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, con
 {
     if (ctx->trsv_block == 64)
         return launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_t, ctx->stream);
-    return launch_trsv_sb_t(U, ldu, n, (const double *)ctx->ws[WS_SB], b, x,
-                            ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t, ctx->stream);
+    return launch_trsv_w_t((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], b, x,
+                           ctx->ctl_t, ctx->stream);
 }
 
 // Sampled kernel timing: events recorded around KI1/KI2/KI3 on the stream;
@@ -201,7 +209,8 @@ struct LzOp {
     const double *Dinv;
     const float *A32; int64_t lda32;
     const float *U32; int64_t ldu32;
-    const double *sb;
+    const float *W32; int64_t ldw32;
+    const double *sb;   // super-block inverses and link blocks of U~
 };
 
 static LzOp op_fp64(const double *A, int64_t lda, const double *U, int64_t ldu, const double *Dinv)
@@ -219,8 +228,7 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
     if (op.f32)
-        TRY(launch_trsv_sb_n_f32(op.U32, op.ldu32, n, op.sb, w, tmp, ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n,
-                                 ctx->stream));
+        TRY(launch_trsv_w_n_f32(op.W32, op.ldw32, n, op.sb, w, tmp, ctx->ctl_n, ctx->stream));
     else
         TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
@@ -230,8 +238,7 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
         TRY(launch_symv(ctx, n, op.A, op.lda, tmp, z));
     if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
     if (op.f32)
-        TRY(launch_trsv_sb_t_f32(op.U32, op.ldu32, n, op.sb, z, z, ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t,
-                                 ctx->stream));
+        TRY(launch_trsv_w_t_f32(op.W32, op.ldw32, n, op.sb, z, z, ctx->ctl_t, ctx->stream));
     else
         TRY(solve_t(ctx, n, op.U, op.ldu, op.Dinv, z, z));
     if (sample) {
@@ -613,16 +620,19 @@ static int mixed_operator(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t l
     float *A32 = (float *)p;
     TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     double *Dinv = (double *)p;
-    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
     double *sb = (double *)p;
+    TRY(ws_get(ctx, WS_W, sizeof(float) * (size_t)ld32 * (size_t)n, &p));
+    float *W32 = (float *)p;
     TRY(launch_to_f32(A, lda, A32, ld32, n, n, ctx->stream));
     if (!have_dinv) TRY(launch_diag_inv_f32(U32, ldu32, n, Dinv, ctx->stream));
-    TRY(launch_make_sb_f32(U32, ldu32, n, Dinv, sb, ctx->stream));
+    TRY(launch_make_w_f32(U32, ldu32, n, Dinv, sb, W32, ld32, ctx->stream));
     *op = LzOp{};
     op->f32 = 1;
     op->Dinv = Dinv;
     op->A32 = A32; op->lda32 = ld32;
     op->U32 = U32; op->ldu32 = ldu32;
+    op->W32 = W32; op->ldw32 = ld32;
     op->sb = sb;
     return 0;
 }
@@ -844,7 +854,8 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     b += sizeof(double) * (size_t)mmax * (size_t)s;               // S
     b += 2 * sizeof(double) * (size_t)ldv * (size_t)s;            // check blocks
     b += sizeof(double) * (size_t)nblk * nblk * NB;               // SYMV column partials
-    b += trsv_sb_bytes(n);                                        // super-block solve data
+    b += trsv_w_side_bytes(n);                                    // super-block inverses, link blocks
+    b += sizeof(double) * (size_t)ldv * (size_t)n;                // W (super-block solves)
     b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
     b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
     if (o.invert) {
@@ -1135,14 +1146,17 @@ int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
     void *p;
     TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     double *Dinv = (double *)p;
-    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
     double *sb = (double *)p;
+    const int64_t ldw = round_ld(n);
+    TRY(ws_get(ctx, WS_W, sizeof(float) * (size_t)ldw * (size_t)n, &p));
+    float *W32 = (float *)p;
     TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
-    TRY(launch_make_sb_f32(U, ldu, n, Dinv, sb, ctx->stream));
+    TRY(launch_make_w_f32(U, ldu, n, Dinv, sb, W32, ldw, ctx->stream));
     if (trans == 0)
-        TRY(launch_trsv_sb_n_f32(U, ldu, n, sb, b, x, ctl_rstage(ctx, ctx->ctl_n), ctx->ctl_n, ctx->stream));
+        TRY(launch_trsv_w_n_f32(W32, ldw, n, sb, b, x, ctx->ctl_n, ctx->stream));
     else
-        TRY(launch_trsv_sb_t_f32(U, ldu, n, sb, b, x, ctl_rstage(ctx, ctx->ctl_t), ctx->ctl_t, ctx->stream));
+        TRY(launch_trsv_w_t_f32(W32, ldw, n, sb, b, x, ctx->ctl_t, ctx->stream));
     return ctl_check(ctx);
 }
 
@@ -1175,13 +1189,14 @@ int gsyeig_trsm_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
     void *p;
     TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
     double *Dinv = (double *)p;
-    TRY(ws_get(ctx, WS_SB, trsv_sb_bytes(n), &p));
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
     double *sb = (double *)p;
     const int64_t ldw = round_ld(n);
     TRY(ws_get(ctx, WS_Y, sizeof(double) * (size_t)ldw * (size_t)k, &p));
     double *W = (double *)p;
     TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
-    TRY(launch_make_sb_f32(U, ldu, n, Dinv, sb, ctx->stream));
+    TRY(launch_sb_inverses_f32(U, ldu, n, Dinv, sb, sb + cdiv(n, trsv_sb_rows()) * trsv_sb_rows() * trsv_sb_rows(),
+                               ctx->stream));
     TRY(launch_blk_copy(V, ldv, W, ldw, n, k, ctx->stream));
     TRY(launch_trsm_sb_f32(trans, U, ldu, n, sb, W, ldw, X, ldx, k, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -61,6 +61,7 @@ enum WsSlot {
     WS_RITZ,       // orthonormalisation of the Ritz coefficient matrix
     WS_ACOPY,      // working copy of A factored by the inverse-pencil solve (FP64 mode)
     WS_INV,        // mu and vectors of the inverse-pencil solve
+    WS_W,          // W = blockdiag(U_SS)^-1 U_offdiag for the super-block solves (FP64 or FP32)
     WS_COUNT
 };
 
@@ -120,23 +121,26 @@ int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
 int64_t gemm_splitk_parts(const GemmDesc &d);
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
-// super-block solves (k_trsv_sb.hip); sb = [Uinv | Uinv^T | N | N']
-int64_t trsv_sb_rows();
-size_t trsv_sb_bytes(int64_t n);
-int launch_make_sb(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
-                   hipStream_t st);
-int launch_trsv_sb_n(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
-                     double *x, double *rstage, PCtl *ctl, hipStream_t st);
-int launch_trsv_sb_t(const double *U, int64_t ldu, int64_t n, const double *sb, const double *b,
-                     double *x, double *rstage, PCtl *ctl, hipStream_t st);
-// FP32-storage variants (mixed mode) and the FP64 -> FP32 copy
-// (U stored FP32, super-block data FP64)
-int launch_trsv_sb_n_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
-                         double *x, double *rstage, PCtl *ctl, hipStream_t st);
-int launch_trsv_sb_t_f32(const float *U, int64_t ldu, int64_t n, const double *sb, const double *b,
-                         double *x, double *rstage, PCtl *ctl, hipStream_t st);
-int launch_make_sb_f32(const float *U, int64_t ldu, int64_t n, const double *Dinv, double *sb,
+// super-block solves (k_trsv_w.hip): Uinv_SS and its transpose per 512-row super-block
+int64_t trsv_sb_rows();  // rows of a diagonal super-block (512)
+int launch_sb_inverses(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *Uinv, double *UinvT,
                        hipStream_t st);
+int launch_sb_inverses_f32(const float *U, int64_t ldu, int64_t n, const double *Dinv, double *Uinv,
+                           double *UinvT, hipStream_t st);
+// sweeps on U = D (I + W) (k_trsv_w.hip); sbw = [Uinv | Uinv^T | W_{S-1,S}^T] per super-block
+size_t trsv_w_side_bytes(int64_t n);
+int launch_make_w(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *sbw, double *W, int64_t ldw,
+                  hipStream_t st);
+int launch_make_w_f32(const float *U, int64_t ldu, int64_t n, const double *Dinv, double *sbw, float *W,
+                      int64_t ldw, hipStream_t st);
+int launch_trsv_w_n(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                    PCtl *ctl, hipStream_t st);
+int launch_trsv_w_t(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                    PCtl *ctl, hipStream_t st);
+int launch_trsv_w_n_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                        PCtl *ctl, hipStream_t st);
+int launch_trsv_w_t_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                        PCtl *ctl, hipStream_t st);
 int launch_potrf_diag_f32(float *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,
                           hipStream_t st);
 int launch_diag_inv_f32(const float *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);

@@ -254,8 +254,7 @@ int launch_gemm(const GemmDesc &d, hipStream_t st)
         // FP32 compute: C stored FP64 or FP32
         rc = d.c_f32 ? run_types<float, float>(a, d, nz, st) : run_types<float, double>(a, d, nz, st);
     } else {
-        if (d.c_f32) return GSYEIG_EHIP;
-        rc = run_types<double, double>(a, d, nz, st);
+        rc = d.c_f32 ? run_types<double, float>(a, d, nz, st) : run_types<double, double>(a, d, nz, st);
     }
     if (rc || nz == 1) return rc;
     const int64_t tot = d.m * d.n;

@@ -1,8 +1,9 @@
 """Mixed-precision path on the GPU, through the C ABI, against the CPU oracle.
 
-* FP32-storage sweeps (KI1/KI3/KI2 with FP32 U or A): the kernels compute in
-  FP64 with the FP32 matrix, so they must match the oracle run on the same
-  FP32 values promoted to FP64, to FP64 accuracy.
+* FP32-storage sweeps: SYMV with FP32 A computes in FP64, so it matches the
+  oracle on the same FP32 values promoted to FP64 to FP64 accuracy; the
+  triangular sweeps keep the off-diagonal factor blocks (W = D^-1 U_offdiag)
+  in FP32 and agree with the oracle to FP32 accuracy.
 * Mixed GS1 (FP32 trailing updates) and the FP32 block solves: FP32-level
   agreement with the FP64 oracle.
 * The small dense eigensolver of the refinement: FP64 agreement with the
@@ -106,9 +107,10 @@ def test_trsv_lp_equals_promoted_oracle(gs, ctx, torch, orc, n, trans):
     assert gs.gsyeig_trsv_lp(ctx, n, Ud, n, trans, bd, xd) == 0
     x = host(xd)
     ref = orc.trsv_upper_t(U, b) if trans else orc.trsv_upper(U, b)
-    # both solve with the same FP64 matrix; only rounding order differs
+    # the sweeps apply U = D (I + W) with W = D^-1 U_offdiag stored in FP32
+    # (D: 512-row diagonal blocks, inverted in FP64): FP32-level agreement
     err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
-    assert err <= 200 * n * U64, err
+    assert err <= 64 * U32, err
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 700, 2049])
