@@ -22,8 +22,11 @@ sys.path.insert(0, ROOT)
 CONFIGS = {
     0: dict(n=512, s=10, law="spaced", label="known-spectrum pencil n=512 s=10, FP64 single-vector KI"),
     1: dict(n=16384, s=100, law="spaced", label="known-spectrum pencil n=16384 s=100, FP64 single-vector KI"),
-    2: dict(n=32768, s=200, law="clustered",
+    2: dict(n=32768, s=200, law="clustered", prec="mixed",
             label="known-spectrum pencil n=32768 s=200, clustered spectrum, mixed FP32 sweeps + FP64 refinement"),
+    3: dict(n=65536, s=800, law="spaced", prec="mixed", block=32,
+            label="known-spectrum pencil n=65536 s=800 + 1-D FEM pencil (inverse pencil), block Lanczos, "
+                  "mixed FP32 block products + FP64 refinement"),
     4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n), FP64"),
 }
 HBM_PEAK_GBS = 8000.0
@@ -88,6 +91,10 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (exploration; the config label then says so)")
     ap.add_argument("--s", type=int, default=0, help="override s")
     ap.add_argument("--no-fp64-compare", action="store_true", help="--config 2: skip the FP64 solve")
+    ap.add_argument("--block", type=int, default=0, help="--config 3: block size (default 32)")
+    ap.add_argument("--basis", type=int, default=0, help="--config 3: basis size before a restart (0 = auto)")
+    ap.add_argument("--acc32", type=int, default=0, help="--config 3: 1 = FP32 accumulation in block products")
+    ap.add_argument("--no-fem", action="store_true", help="--config 3: skip the FEM pencil")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -116,6 +123,8 @@ def main():
         return bench_batched(args, cfg)
     if args.config == 2:
         return bench_mixed(args, cfg)
+    if args.config == 3:
+        return bench_block(args, cfg)
     n, s = cfg["n"], cfg["s"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -210,29 +219,157 @@ def main():
 def trsv_only(args, cfg):
     """KI1 and KI3 alone (no eigen-solve, no QR): the workload of the byte-
     counter passes.  Also one device copy of n^2 FP64 values, whose read and
-    written bytes are known exactly, to calibrate the counters."""
+    written bytes are known exactly, to calibrate the counters.  For the mixed
+    configuration the factor is stored FP32 and the FP32-matrix sweeps run."""
     import torch
 
     import paper_1111_6374_amd as gs
 
     n = args.n or cfg["n"]
+    lp = cfg.get("prec") == "mixed"
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(6374)
     U = torch.triu(torch.randn(n, n, generator=g, device=dev, dtype=torch.float64) / math.sqrt(n), 1)
     U.diagonal().copy_(1.0 + torch.rand(n, generator=g, device=dev, dtype=torch.float64))
+    U32 = U.float() if lp else None
     b = torch.randn(n, generator=g, device=dev, dtype=torch.float64)
     x = torch.empty_like(b)
     C = torch.empty_like(U)
     with gs.Solver() as sv:
         for trans in (0, 1):
             for _ in range(max(1, args.steps)):
-                rc = gs.gsyeig_trsv(sv.ctx, n, U, n, trans, b, x)
+                if lp:
+                    rc = gs.gsyeig_trsv_lp(sv.ctx, n, U32, n, trans, b, x)
+                else:
+                    rc = gs.gsyeig_trsv(sv.ctx, n, U, n, trans, b, x)
                 if rc:
-                    raise gs.GsyeigError("gsyeig_trsv", rc)
+                    raise gs.GsyeigError("gsyeig_trsv_lp" if lp else "gsyeig_trsv", rc)
         C.copy_(U)  # reads and writes 8 n^2 bytes
         torch.cuda.synchronize()
-    log(f"trsv-only n={n}: {2 * max(1, args.steps)} solves and one copy of {8 * n * n} bytes done")
+    log(f"trsv-only n={n} ({'FP32' if lp else 'FP64'} factor): {2 * max(1, args.steps)} solves and one copy of "
+        f"{8 * n * n} bytes done")
+
+
+def bench_block(args, cfg):
+    """Block Lanczos in mixed precision on the known-spectrum pencil (the timed
+    workload) and on the 1-D FEM pencil through the inverse pencil (checked
+    against its closed form, timed once)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1111_6374_amd as gs
+
+    n, s = cfg["n"], cfg["s"]
+    blk = args.block or cfg["block"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating n={n} s={s} law={cfg['law']} (device draws)")
+    t0 = time.perf_counter()
+    inst = gen.known_spectrum_device(n, cfg["law"], seed=gen.BASE_SEED + 3, stream=(3, 0, 0), device=dev,
+                                     keep_factors=False, rng_kind="torch")
+    A, B0 = inst["A"], inst["B"]
+    lam_true = np.sort(inst["lam"])[:s]
+    B = torch.empty_like(B0)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    solver = gs.Solver()
+    Lam = torch.empty(s, dtype=torch.float64, device=dev)
+    X = torch.empty(s, n, dtype=torch.float64, device=dev)
+
+    def opts(**kw):
+        o = gs.gsyeig_opts_default()
+        o.prec = gs.GSYEIG_MIXED
+        o.block = blk
+        o.basis = args.basis
+        o.block_acc32 = args.acc32
+        o.profile_every = args.profile_every
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def run(Am, Bm, Bsrc, o):
+        if Bsrc is not None:
+            Bm.copy_(Bsrc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, info = gs.gsyeig_solve(solver.ctx, n, s, Am, n, Bm, n, o, Lam, X, n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if rc:
+            raise gs.GsyeigError("gsyeig_solve", rc)
+        return dt, info
+
+    def show(tag, dt, inf):
+        log(f"{tag}: {dt:.2f} s (GS1 {inf.t_gs1_ms:.0f} ms, KI {inf.t_ki_ms:.0f} [projected solves "
+            f"{inf.t_rr_ms:.0f} in {inf.rr_count}], KI5 {inf.t_ki5_ms:.0f}, BT1 {inf.t_bt1_ms:.0f}, refine "
+            f"{inf.t_refine_ms:.0f}, check {inf.t_check_ms:.0f}) ops={inf.steps} restarts={inf.restarts} "
+            f"basis={inf.basis} kept={inf.kept} eta={inf.eta_max:.2e} eta1={inf.eta_phase1:.2e} "
+            f"rounds={inf.refine_iters}")
+
+    for w in range(args.warmup):
+        dt, inf = run(A, B, B0, opts())
+        show("warmup", dt, inf)
+    times, infos = [], []
+    for k in range(args.steps):
+        dt, inf = run(A, B, B0, opts())
+        show(f"step {k}", dt, inf)
+        times.append(dt)
+        infos.append(inf)
+    lam_b = Lam.cpu().numpy()
+    mx = float(np.max(np.abs(inst["lam"])))
+    e_lam = float(np.max(np.abs(lam_b - lam_true)) / mx)
+    value = sum(times) / len(times)
+    last = infos[-1]
+    samples = sum(i.prof_samples for i in infos)
+    t1 = sum(i.t_ki1_ms_sum for i in infos) / max(samples, 1)
+    t2 = sum(i.t_ki2_ms_sum for i in infos) / max(samples, 1)
+    t3 = sum(i.t_ki3_ms_sum for i in infos) / max(samples, 1)
+    # one block application: two triangular block solves (n^2 b flops each)
+    # and the symmetric product on the full A~ (2 n^2 b)
+    flops = 4.0 * n * n * blk
+    t_app = t1 + t2 + t3
+    tf = flops / (t_app * 1e-3) / 1e12 if t_app > 0 else None
+    peak = 157.3 if args.acc32 else 78.6
+    del A, B, B0, inst
+    torch.cuda.empty_cache()
+    fem = None
+    if not args.no_fem:
+        K, M = gen.fem_pencil_device(n, dev)
+        lam_ref, _ = gen.fem_eigs(n, s)
+        dtf, inff = run(K, M, None, opts(invert=1))
+        show("fem (inverse pencil)", dtf, inff)
+        lam_f = Lam.cpu().numpy()
+        fem = {"time_s": dtf, "operator_applications": int(inff.steps), "restarts": int(inff.restarts),
+               "max_rel_err_vs_closed_form": float(np.max(np.abs(lam_f - lam_ref) / lam_ref)),
+               "eta_max": inff.eta_max, "omega": inff.omega}
+        del K, M
+    out = {
+        "metric": "time-to-s-eigenpairs", "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "mixed",
+                   "block": blk, "block_products": "fp32-acc" if args.acc32 else "fp64-acc",
+                   "operator_applications": int(last.steps), "restarts": int(last.restarts),
+                   "basis": int(last.basis), "kept": int(last.kept), "refine_rounds": int(last.refine_iters),
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                     "frac": (tf / peak) if tf else None, "traffic": None,
+                     "kernel": "k_gemm (block operator: TRSM, SYMM, TRSM)", "avg_launch_ms": t_app,
+                     "algorithmic_flops_per_application": flops},
+        "kernels": {"trsm_n_ms": t1, "symm_ms": t2, "trsm_t_ms": t3, "samples": samples},
+        "stages_ms": {"gs1": last.t_gs1_ms, "ki_loop": last.t_ki_ms, "projected_solves": last.t_rr_ms,
+                      "ki5": last.t_ki5_ms, "bt1": last.t_bt1_ms, "refine": last.t_refine_ms,
+                      "check": last.t_check_ms, "total": last.t_total_ms},
+        "parity": {"e_lambda_vs_known": e_lam, "eta_max": last.eta_max, "omega": last.omega, "rho_F": last.rho_f,
+                   "pass": bool(e_lam <= 1e-10 and last.eta_max <= 1e-10)},
+        "fem_inverse_pencil": fem,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, cfg["law"])
+    print(json.dumps(out), flush=True)
 
 
 def bench_mixed(args, cfg):

@@ -164,6 +164,21 @@ def fem_pencil(n: int):
     return K, M
 
 
+def fem_pencil_device(n: int, device="cuda"):
+    """``fem_pencil(n)`` assembled directly on a torch device (same values)."""
+    import torch
+
+    h = 1.0 / (n + 1)
+    K = torch.zeros(n, n, dtype=torch.float64, device=device)
+    M = torch.zeros(n, n, dtype=torch.float64, device=device)
+    K.diagonal().fill_(2.0 / h)
+    M.diagonal().fill_(4.0 * h / 6.0)
+    for off in (1, -1):
+        K.diagonal(off).fill_(-1.0 / h)
+        M.diagonal(off).fill_(h / 6.0)
+    return K, M
+
+
 def fem_eigs(n: int, s: int):
     """Closed form of the s smallest eigenpairs of ``fem_pencil(n)``.
 

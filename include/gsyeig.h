@@ -96,10 +96,21 @@ typedef struct {
                            /*   pass only when the first kept less than 1/sqrt(2) */
                            /*   of the norm (orthogonality monitored and amended, */
                            /*   the alternative Sec. 2.3 names)                   */
+    /* block Lanczos (block > 1) */
+    int64_t basis;         /* most basis vectors before a thick restart (0 =     */
+                           /*   min(8192, n - block, max(keep + 4 block, 5 s)))   */
+    int64_t keep;          /* Ritz vectors kept at a restart (0 = the extracted  */
+                           /*   pairs, at least min(2 s, 4096, (n - block) / 2))  */
+    int64_t block_acc32;   /* mixed mode: 1 = block products accumulate in FP32  */
+                           /*   (FP32 MFMA; the Lanczos tolerance is then no     */
+                           /*   finer than 64 u_32 = 3.8e-6, the refinement      */
+                           /*   finishes the pairs); 0 (default) = FP64           */
+                           /*   accumulation of the FP32-stored matrices          */
 } gsyeig_opts;
 
 typedef struct {
-    int64_t steps;         /* Lanczos steps m actually taken                       */
+    int64_t steps;         /* Lanczos steps m actually taken (block Lanczos:      */
+                           /*   operator applications, b per block step)          */
     int64_t converged;     /* wanted pairs whose Ritz residual met tol             */
     double eta_max;        /* max_i ||A x_i - l_i B x_i|| / ((||A||F+|l_i| ||B||F)||x_i||) */
     double rho_f;          /* ||A X - B X L||_F / max(||A||_F, ||B||_F) (Tables 3/7) */
@@ -124,6 +135,12 @@ typedef struct {
     int64_t refine_iters;  /* correction rounds taken                           */
     int64_t block_applies; /* FP32 block operator applications (block_cols wide)*/
     int64_t block_cols;    /* width of the refinement block (s + guard)         */
+    /* block Lanczos (opts.block > 1) */
+    int64_t restarts;      /* thick restarts taken                              */
+    int64_t basis;         /* basis size at which it restarts                   */
+    int64_t kept;          /* Ritz vectors kept at a restart                    */
+    double t_rr_ms;        /* projected eigen-solves of the checks (in t_ki_ms) */
+    int64_t rr_count;      /* number of those                                   */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */
@@ -239,8 +256,10 @@ int gsyeig_trsm_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
  * refinement (Rayleigh-Ritz, Section 2.3 step "eigenpairs of the projected
  * matrix"): the nwant smallest (which = 0) or largest (which = 1)
  * eigenpairs of the symmetric N x N matrix H (device, column-major, ldh;
- * only read), N <= 2048, by Householder tridiagonalisation, Sturm bisection,
- * inverse iteration (orthogonalised in clusters) and back-transformation.
+ * only read), N <= 8192, by Householder tridiagonalisation, Sturm bisection,
+ * inverse iteration (made orthonormal by Cholesky QR twice; Gram-Schmidt in
+ * clusters of near-equal values when that finds near-parallel vectors) and
+ * back-transformation.
  * w (device, nwant) ascending; Q (device, N x nwant column-major, ldq)
  * orthonormal.  Synchronises. */
 int gsyeig_syev_small(gsyeig_ctx *ctx, int64_t N, const double *H, int64_t ldh, int64_t nwant, int which,
@@ -249,7 +268,7 @@ int gsyeig_syev_small(gsyeig_ctx *ctx, int64_t N, const double *H, int64_t ldh, 
 /* FP64 refinement of the mixed-precision path (Rayleigh-Ritz on the
  * ORIGINAL pencil of Eq. 1 with correction expansion; the paper ran FP64
  * only, Section 3).  Starting block X0 (device, n x k column-major, k >= s,
- * 2k <= 2048; e.g. U~^-1 times Ritz vectors of the FP32-sweep Lanczos):
+ * 2k <= 8192; e.g. U~^-1 times Ritz vectors of the FP32-sweep Lanczos):
  *   repeat: B-orthonormalise; Rayleigh-Ritz with FP64 A X and B X;
  *           R = A X - B X Theta; stop when the wanted s pairs have
  *           eta_i = ||r_i|| / ((||A||_F + |theta_i| ||B||_F) ||x_i||)

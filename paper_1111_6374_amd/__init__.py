@@ -55,7 +55,10 @@ class gsyeig_opts(ctypes.Structure):
                 ("check_every", ctypes.c_int64), ("seed", ctypes.c_uint64), ("v0", ctypes.c_void_p),
                 ("profile_every", ctypes.c_int64), ("eta_tol", ctypes.c_double),
                 ("refine_iters", ctypes.c_int64), ("refine_inner", ctypes.c_int64), ("guard", ctypes.c_int64),
-                ("reorth", ctypes.c_int64)]
+                ("reorth", ctypes.c_int64),
+                ("basis", ctypes.c_int64),
+                ("keep", ctypes.c_int64),
+                ("block_acc32", ctypes.c_int64)]
 
 
 class gsyeig_info(ctypes.Structure):
@@ -65,7 +68,9 @@ class gsyeig_info(ctypes.Structure):
         ("prof_samples", ctypes.c_int64), ("t_ki1_ms_sum", ctypes.c_double),
         ("t_ki2_ms_sum", ctypes.c_double), ("t_ki3_ms_sum", ctypes.c_double),
         ("t_refine_ms", ctypes.c_double), ("eta_phase1", ctypes.c_double), ("refine_iters", ctypes.c_int64),
-        ("block_applies", ctypes.c_int64), ("block_cols", ctypes.c_int64)]
+        ("block_applies", ctypes.c_int64), ("block_cols", ctypes.c_int64), ("restarts", ctypes.c_int64),
+        ("basis", ctypes.c_int64), ("kept", ctypes.c_int64), ("t_rr_ms", ctypes.c_double),
+        ("rr_count", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -186,6 +186,21 @@ static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, con
                            ctx->ctl_t, ctx->stream);
 }
 
+// Super-block inverses of an FP64 factor for the block solves: built with
+// the factor's side data by the super-block sweeps, else built here.
+static int block_sb_fp64(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
+                         const double **sb)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
+    if (ctx->trsv_block == 64) {
+        const int64_t SB = trsv_sb_rows();
+        TRY(launch_sb_inverses(U, ldu, n, Dinv, (double *)p, (double *)p + cdiv(n, SB) * SB * SB, ctx->stream));
+    }
+    *sb = (const double *)p;
+    return 0;
+}
+
 // Sampled kernel timing: events recorded around KI1/KI2/KI3 on the stream;
 // harvested (elapsed times summed) at the next synchronisation point.
 static int prof_harvest(gsyeig_ctx *ctx)
@@ -258,7 +273,7 @@ static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double
 // of the computed vectors is as good.  *info_d != 0 if G was not positive
 // definite or if two columns overlapped by more than 1e-8 (the caller then
 // falls back to sequential Gram-Schmidt with extra inverse-iteration solves).
-static int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d)
+int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d)
 {
     const int64_t nwr = cdiv(nw, NB) * NB;
     const int64_t sk = std::max<int64_t>(1, std::min<int64_t>(32, cdiv(m, 1024)));
@@ -612,7 +627,7 @@ static int check_enqueue(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A,
 // FP32 operator data for a factor U~ (FP32): A~ = fl32(A), the FP64 inverses
 // of U~'s diagonal blocks and its super-block inverses.
 static int mixed_operator(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const float *U32,
-                          int64_t ldu32, bool have_dinv, LzOp *op)
+                          int64_t ldu32, bool have_dinv, LzOp *op, bool need_w = true)
 {
     const int64_t ld32 = round_ld(n);
     void *p;
@@ -622,11 +637,17 @@ static int mixed_operator(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t l
     double *Dinv = (double *)p;
     TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
     double *sb = (double *)p;
-    TRY(ws_get(ctx, WS_W, sizeof(float) * (size_t)ld32 * (size_t)n, &p));
-    float *W32 = (float *)p;
+    float *W32 = nullptr;
     TRY(launch_to_f32(A, lda, A32, ld32, n, n, ctx->stream));
     if (!have_dinv) TRY(launch_diag_inv_f32(U32, ldu32, n, Dinv, ctx->stream));
-    TRY(launch_make_w_f32(U32, ldu32, n, Dinv, sb, W32, ld32, ctx->stream));
+    if (need_w) {
+        TRY(ws_get(ctx, WS_W, sizeof(float) * (size_t)ld32 * (size_t)n, &p));
+        W32 = (float *)p;
+        TRY(launch_make_w_f32(U32, ldu32, n, Dinv, sb, W32, ld32, ctx->stream));
+    } else {  // block solves need only the super-block inverses
+        const int64_t SB = trsv_sb_rows();
+        TRY(launch_sb_inverses_f32(U32, ldu32, n, Dinv, sb, sb + cdiv(n, SB) * SB * SB, ctx->stream));
+    }
     *op = LzOp{};
     op->f32 = 1;
     op->Dinv = Dinv;
@@ -659,7 +680,7 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
     TRY(potrf_mixed_enqueue(ctx, n, B, ldb, U32, ld32, Dinv, info_d));
     LzOp op;
-    TRY(mixed_operator(ctx, n, A, lda, U32, ld32, true, &op));
+    TRY(mixed_operator(ctx, n, A, lda, U32, ld32, true, &op, o.block == 1));
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
     int *hi = (int *)ctx->host_pinned;
     HIP_TRY(hipMemcpyAsync(hi, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -672,7 +693,17 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     TRY(ws_get(ctx, WS_BDIAG, sizeof(double) * (size_t)(n + 8), &p));
     double *theta_k = (double *)p;
     LzResult r{};
-    TRY(lz_solve(ctx, n, s, k, op, &o, theta_k, Y, ldy, &r));
+    BlzResult br{};
+    if (o.block > 1) {
+        BlkOp bop{U32, 1, ld32, op.sb, op.A32, 1, ld32, o.block_acc32 ? 1 : 0};
+        TRY(blz_solve(ctx, n, s, k, bop, &o, theta_k, Y, ldy, &br));
+        r.steps = br.steps;
+        r.nconv = br.nconv;
+        r.t_loop_ms = br.t_loop_ms;
+        r.t_ritz_ms = br.t_ritz_ms;
+    } else {
+        TRY(lz_solve(ctx, n, s, k, op, &o, theta_k, Y, ldy, &r));
+    }
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     TRY(launch_backsolve_f32(U32, ld32, n, k, Dinv, Y, ldy, ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
@@ -711,6 +742,11 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     inf.refine_iters = rs.iters;
     inf.block_applies = rs.block_applies;
     inf.block_cols = rs.kept;
+    inf.restarts = br.restarts;
+    inf.basis = br.basis;
+    inf.kept = br.keep;
+    inf.t_rr_ms = br.t_rr_ms;
+    inf.rr_count = br.rr_count;
     if (info) *info = inf;
     return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
 }
@@ -749,7 +785,18 @@ static int solve_inverted(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A
     const int rc = gsyeig_solve(ctx, n, s, B, ldb, Af, ldf, &oi, mu, Xi, ldw, &inf);
     if (rc != 0 && rc != GSYEIG_ENOCONV) return rc;
     HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
-    TRY(launch_invert_pairs(mu, Xi, ldw, Lambda, X, ldx, n, s, ctx->stream));
+    // FP64 Rayleigh-Ritz of (A, B) on span(X): the inverted pairs are only as
+    // B-orthogonal as they are accurate (residual / gap); projecting the
+    // original pencil makes X^T B X = I to rounding and can only improve the
+    // pairs.  No correction rounds (the operator is not used).
+    double *X0;
+    int64_t ld0;
+    TRY(refine_x0(ctx, n, s, &X0, &ld0));
+    TRY(launch_invert_pairs(mu, Xi, ldw, Lambda, X0, ld0, n, s, ctx->stream));
+    RefineOp nop{};
+    RefineCfg rcfg{o.eta_tol, 0, 0};
+    RefineStats rrs{};
+    TRY(refine_run(ctx, n, s, s, 0, A, lda, B, ldb, nop, rcfg, Lambda, X, ldx, &rrs));
     TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
     double *res_d = (double *)ctx->dscal + 64;
     TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, nullptr, Lambda, X, ldx, res_d));
@@ -858,6 +905,11 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     b += sizeof(double) * (size_t)ldv * (size_t)n;                // W (super-block solves)
     b += sizeof(double) * (size_t)nblk * cdiv(nblk, 4) * NB;      // SYMV row partials
     b += sizeof(double) * (size_t)(lz_red_parts(n) * (mmax + 8) + 4 * n + 2048);
+    if (o.block > 1) {
+        const int64_t nv = (o.prec == GSYEIG_MIXED) ? mixed_block(n, s, &o) : s;
+        if (blz_check_dims(n, s, nv, &o)) return -8;
+        b += blz_bytes(n, s, nv, &o);                                 // block basis, projected matrix
+    }
     if (o.invert) {
         b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
         if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
@@ -1008,9 +1060,19 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
     if (ldy < n) return -11;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
-    if (o.prec != GSYEIG_FP64 || o.block != 1 || o.invert) return -8;
+    if (o.prec != GSYEIG_FP64 || o.block < 1 || o.invert) return -8;
+    if (o.block > 1) TRY(blz_check_dims(n, s, s, &o));
     double *Dinv;
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    if (o.block > 1) {
+        const double *sb;
+        TRY(block_sb_fp64(ctx, n, U, ldu, Dinv, &sb));
+        BlkOp bop{U, 0, ldu, sb, A, 0, lda, 0};
+        BlzResult br{};
+        TRY(blz_solve(ctx, n, s, s, bop, &o, theta, Y, ldy, &br));
+        if (steps_out) *steps_out = br.steps;
+        return (br.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+    }
     LzResult r{};
     TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, U, ldu, Dinv), &o, theta, Y, ldy, &r));
     if (steps_out) *steps_out = r.steps;
@@ -1073,9 +1135,10 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (ldb < n) return -7;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
-    if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block != 1 || (o.invert != 0 && o.invert != 1) ||
+    if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block < 1 || (o.invert != 0 && o.invert != 1) ||
         (o.which != 0 && o.which != 1))
         return -8;
+    if (o.block > 1) TRY(blz_check_dims(n, s, o.prec == GSYEIG_MIXED ? mixed_block(n, s, &o) : s, &o));
     if (!Lambda) return -9;
     if (!X) return -10;
     if (ldx < n) return -11;
@@ -1099,7 +1162,19 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (hi[0] != 0) return hi[0];
 
     LzResult r{};
-    TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r));
+    BlzResult br{};
+    if (o.block > 1) {
+        const double *sb;
+        TRY(block_sb_fp64(ctx, n, B, ldb, Dinv, &sb));
+        BlkOp bop{B, 0, ldb, sb, A, 0, lda, 0};
+        TRY(blz_solve(ctx, n, s, s, bop, &o, Lambda, X, ldx, &br));
+        r.steps = br.steps;
+        r.nconv = br.nconv;
+        r.t_loop_ms = br.t_loop_ms;
+        r.t_ritz_ms = br.t_ritz_ms;
+    } else {
+        TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r));
+    }
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
     TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
@@ -1128,6 +1203,11 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.t_ki1_ms_sum = ctx->prof_ms[0];
     inf.t_ki2_ms_sum = ctx->prof_ms[1];
     inf.t_ki3_ms_sum = ctx->prof_ms[2];
+    inf.restarts = br.restarts;
+    inf.basis = br.basis;
+    inf.kept = br.keep;
+    inf.t_rr_ms = br.t_rr_ms;
+    inf.rr_count = br.rr_count;
     if (info) *info = inf;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
 }
@@ -1220,7 +1300,7 @@ int gsyeig_syev_small(gsyeig_ctx *ctx, int64_t N, const double *H, int64_t ldh, 
     TRY(ws_get(ctx, WS_S, need, &p));
     double *Hc = (double *)p, *Qc = Hc + N * N, *wc = Qc + N * nwant, *scr = wc + nwant + 8;
     TRY(launch_blk_copy(H, ldh, Hc, N, N, N, ctx->stream));
-    TRY(syev_small(N, Hc, nwant, which, wc, Qc, scr, ctx->stream));
+    TRY(syev_small(ctx, N, Hc, nwant, which, wc, Qc, scr, ctx->stream));
     TRY(launch_copy(wc, w, nwant, ctx->stream));
     TRY(launch_blk_copy(Qc, N, Q, ldq, N, nwant, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -62,6 +62,7 @@ enum WsSlot {
     WS_ACOPY,      // working copy of A factored by the inverse-pencil solve (FP64 mode)
     WS_INV,        // mu and vectors of the inverse-pencil solve
     WS_W,          // W = blockdiag(U_SS)^-1 U_offdiag for the super-block solves (FP64 or FP32)
+    WS_BLZ,        // block Lanczos: projected matrix, Ritz coefficients, blocks, kept Ritz vectors
     WS_COUNT
 };
 
@@ -222,6 +223,8 @@ int refine_run(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t k, int which, cons
                double *X, int64_t ldx, RefineStats *out);
 int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const double *sb, double *V,
                        int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st);
+int launch_trsm_sb(int trans, const void *U, int u_f32, int64_t ldu, int64_t n, const double *sb, double *V,
+                   int64_t ldv, double *X, int64_t ldx, int64_t k, int f32, hipStream_t st);
 int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
                     hipStream_t st);
 int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st);
@@ -230,9 +233,35 @@ int launch_invert_pairs(const double *mu, const double *Xin, int64_t ldi, double
 int launch_accum_info(const int *src, int *dst, hipStream_t st);        // *dst = *src if *dst == 0
 int launch_flag_offdiag(const double *G, int64_t r, double thresh, int *flag, hipStream_t st);
 size_t syev_small_scratch(int64_t N, int64_t nwant);
-int syev_small(int64_t N, double *H, int64_t nwant, int which, double *w, double *Q, double *scratch,
-               hipStream_t st);
+// ctx != NULL: eigenvectors by independent inverse iteration made orthonormal
+// by Cholesky QR twice, the clustered Gram-Schmidt path only when that finds
+// near-parallel vectors (synchronises); ctx == NULL: always clustered.
+int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
+               double *scratch, hipStream_t st);
+// Cholesky QR twice on the nw columns of S (m x nw, column-major); *info_d
+// != 0 when the Gram matrix was not positive definite or two columns
+// overlapped by more than 1e-8 (two device ints)
+int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d);
 int64_t syev_small_max();
+
+// block Lanczos with thick restart (blz.hip)
+struct BlkOp {             // C = U^-T A U^-1 on blocks (TRSM, SYMM on the matrix cores)
+    const void *U; int u_f32; int64_t ldu;
+    const double *sb;      // super-block inverses of U (FP64)
+    const void *A; int a_f32; int64_t lda;
+    int f32;               // FP32 products with FP32 accumulation (else FP64)
+};
+struct BlzResult {
+    int64_t steps;         // operator applications (columns)
+    int64_t nconv, restarts, breakdowns, basis, keep;
+    float t_loop_ms, t_ritz_ms;
+    double t_rr_ms;        // projected eigen-solves (inside the loop)
+    int64_t rr_count;
+};
+size_t blz_bytes(int64_t n, int64_t s, int64_t nvec, const gsyeig_opts *o);
+int blz_check_dims(int64_t n, int64_t s, int64_t nvec, const gsyeig_opts *o);
+int blz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const BlkOp &op, const gsyeig_opts *o,
+              double *theta_out, double *Y, int64_t ldy, BlzResult *res);
 
 // accuracy check
 int fro_parts(int64_t n);

@@ -21,10 +21,11 @@
 // Accuracy is decided by the FP64 steps (A X, B X, the projected matrices,
 // the residual); the FP32 part only changes how fast the loop converges.
 //
-// The small projected eigenproblems (order <= 2048) are solved by a
-// one-workgroup Householder tridiagonalisation, the tridiagonal
-// bisection/inverse-iteration kernels of the Lanczos path, and the
-// reflectors applied back.
+// The small projected eigenproblems (order <= 8192) are solved by a
+// Householder tridiagonalisation (one workgroup up to order 192, the whole
+// GPU above), the tridiagonal bisection/inverse-iteration kernels of the
+// Lanczos path with Cholesky-QR orthonormalisation, and the reflectors
+// applied back.
 #include <string.h>
 
 #include <algorithm>
@@ -35,9 +36,16 @@
 namespace {
 
 constexpr int CHUNK = 4096;        // rows per partial sum in column reductions
-constexpr int SYTRD_MAX = 2048;    // largest order of the small eigensolver
+constexpr int SYTRD_LDS = 256;     // largest order reduced by the one-workgroup kernel
+constexpr int SYTRD_MAX = 8192;    // largest order of the small eigensolver
 
 inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
+
+#define RTRY_HIP(expr)           \
+    do {                         \
+        int _rc = (expr);        \
+        if (_rc) return _rc;     \
+    } while (0)
 
 __device__ __forceinline__ double block_sum256(double v, double *sb)
 {
@@ -349,8 +357,8 @@ __global__ void k_svqb_coef(const double *V, int64_t r, const double *sig, const
 __global__ __launch_bounds__(1024) void k_sytrd(double *W, int64_t ldw, int N, double *d, double *e,
                                                 double *tau)
 {
-    __shared__ double v[SYTRD_MAX];
-    __shared__ double q[SYTRD_MAX];
+    __shared__ double v[SYTRD_LDS];
+    __shared__ double q[SYTRD_LDS];
     __shared__ double red[16];
     const int tid = threadIdx.x;
     for (int j = 0; j + 2 < N; ++j) {
@@ -413,6 +421,128 @@ __global__ __launch_bounds__(1024) void k_sytrd(double *W, int64_t ldw, int N, d
         e[N - 2] = W[(int64_t)(N - 2) * ldw + (N - 1)];
         tau[N - 2] = 0.0;
     }
+}
+
+// The same reduction spread over the whole GPU: per column j, one
+// workgroup (k_trd_col) finishes q_{j-1}, applies update j-1 to column j
+// and forms reflector j; then a grid of tiles (k_trd_upd) applies update
+// j-1 to the trailing columns and, in the same pass over the updated
+// entries, forms the partial products of p_j = tau_j A22 v_j.  The matrix
+// is read and written once per column.  Reflectors, d, e and tau are left
+// exactly as k_sytrd leaves them.
+//   vbuf: 2 x N (v_j in vbuf[j % 2], absolute row index), qbuf: N,
+//   ppart: ceil(N / TRD_TC) x N partial sums of p_j.
+constexpr int TRD_TC = 64;  // trailing columns per tile of k_trd_upd
+
+__global__ __launch_bounds__(1024) void k_trd_col(double *W, int64_t ldw, int N, int j, double *d, double *e,
+                                                  double *tau, double *vbuf, double *qbuf, const double *ppart,
+                                                  int npart, int last)
+{
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    if (N == 1) {
+        if (tid == 0) d[0] = W[0];
+        return;
+    }
+    const double *vprev = vbuf + (int64_t)((j + 1) & 1) * N;
+    double *vcur = vbuf + (int64_t)(j & 1) * N;
+    const double tp = (j > 0) ? tau[j - 1] : 0.0;
+    if (tp != 0.0) {
+        // p_{j-1} (tau included) on rows j.., K = tau/2 p^T v, q = p - K v
+        double pv = 0.0;
+        for (int t = j + tid; t < N; t += 1024) {
+            double p = 0.0;
+            for (int c = 0; c < npart; ++c) p += ppart[(int64_t)c * N + t];
+            qbuf[t] = p;
+            pv = fma(p, vprev[t], pv);
+        }
+        const double K = 0.5 * tp * block_sum1024(pv, red);
+        for (int t = j + tid; t < N; t += 1024) qbuf[t] = fma(-K, vprev[t], qbuf[t]);
+        __syncthreads();
+        // column j (and, at the end, column j + 1) on rows j..: A -= v q^T + q v^T
+        const int ncol = last ? 2 : 1;
+        for (int c = 0; c < ncol; ++c) {
+            const int l = j + c;
+            const double ql = qbuf[l], vl = vprev[l];
+            for (int t = l + tid; t < N; t += 1024) {
+                double *a = &W[(int64_t)l * ldw + t];
+                *a = *a - vprev[t] * ql - qbuf[t] * vl;
+            }
+        }
+        __syncthreads();
+    }
+    if (last) {  // j = N - 2: the trailing 2 x 2 block
+        if (tid == 0) {
+            d[N - 2] = W[(int64_t)(N - 2) * ldw + (N - 2)];
+            d[N - 1] = W[(int64_t)(N - 1) * ldw + (N - 1)];
+            e[N - 2] = W[(int64_t)(N - 2) * ldw + (N - 1)];
+            tau[N - 2] = 0.0;
+        }
+        return;
+    }
+    if (tid == 0) d[j] = W[(int64_t)j * ldw + j];
+    // reflector j from x = A[j+1:N, j]
+    const int m = N - j - 1;
+    double *col = W + (int64_t)j * ldw + (j + 1);
+    double ss = 0.0;
+    for (int t = 1 + tid; t < m; t += 1024) ss = fma(col[t], col[t], ss);
+    ss = block_sum1024(ss, red);
+    const double alpha = col[0];
+    double tj = 0.0, ej = alpha, scale = 0.0;
+    if (ss > 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        ej = beta;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        tau[j] = tj;
+        e[j] = ej;
+    }
+    for (int t = tid; t < m; t += 1024) {
+        const double vt = (t == 0) ? 1.0 : col[t] * scale;
+        vcur[j + 1 + t] = (tj != 0.0) ? vt : 0.0;
+        if (tj != 0.0) col[t] = vt;
+    }
+}
+
+// Trailing columns l >= j+1 on rows t >= j+1: update j-1, then partial
+// sums over this tile's columns of tau_j A(t, l) v_j(l).
+__global__ __launch_bounds__(256) void k_trd_upd(double *W, int64_t ldw, int N, int j, const double *tau,
+                                                 const double *vbuf, const double *qbuf, double *ppart)
+{
+    __shared__ double s_v[TRD_TC], s_q[TRD_TC], s_w[TRD_TC];
+    const double *vprev = vbuf + (int64_t)((j + 1) & 1) * N;
+    const double *vcur = vbuf + (int64_t)(j & 1) * N;
+    const int r0 = j + 1;
+    const int t = r0 + blockIdx.x * 256 + threadIdx.x;
+    const int l0 = r0 + blockIdx.y * TRD_TC;
+    const double tp = (j > 0) ? tau[j - 1] : 0.0;
+    const double tj = tau[j];
+    if (threadIdx.x < TRD_TC) {
+        const int l = l0 + threadIdx.x;
+        const bool in = l < N;
+        s_v[threadIdx.x] = (in && tp != 0.0) ? vprev[l] : 0.0;
+        s_q[threadIdx.x] = (in && tp != 0.0) ? qbuf[l] : 0.0;
+        s_w[threadIdx.x] = in ? vcur[l] : 0.0;
+    }
+    __syncthreads();
+    if (t >= N) return;
+    const double vt = (tp != 0.0) ? vprev[t] : 0.0, qt = (tp != 0.0) ? qbuf[t] : 0.0;
+    const int lend = min(TRD_TC, N - l0);
+    double acc = 0.0;
+    double *a = W + (int64_t)l0 * ldw + t;
+    if (tp != 0.0) {
+        for (int c = 0; c < lend; ++c) {
+            const double x = a[(int64_t)c * ldw] - vt * s_q[c] - qt * s_v[c];
+            a[(int64_t)c * ldw] = x;
+            acc = fma(x, s_w[c], acc);
+        }
+    } else {
+        for (int c = 0; c < lend; ++c) acc = fma(a[(int64_t)c * ldw], s_w[c], acc);
+    }
+    ppart[(int64_t)blockIdx.y * N + t] = tj * acc;
 }
 
 // S <- H_0 H_1 ... H_{N-3} S for the reflectors left by k_sytrd; one
@@ -549,40 +679,83 @@ int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, in
 
 size_t syev_small_scratch(int64_t N, int64_t nwant)
 {
-    return sizeof(double) * (size_t)(3 * N + 8 + 7 * N * nwant);
+    return sizeof(double) * (size_t)(3 * N + 8 + 7 * N * nwant + 3 * N + cdiv(N, TRD_TC) * N + 64);
+}
+
+// Householder tridiagonalisation of H (N x N, ld N): one workgroup for small
+// orders, the whole GPU (two launches per column) above.
+static int sytrd_launch(int64_t N, double *H, double *d, double *e, double *tau, double *aux, hipStream_t st)
+{
+    if (N <= 192) {  // <= SYTRD_LDS
+        hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, st, H, N, (int)N, d, e, tau);
+        return ok();
+    }
+    double *vbuf = aux, *qbuf = vbuf + 2 * N, *ppart = qbuf + N;
+    for (int64_t j = 0; j + 2 < N; ++j) {
+        const int64_t m = N - j - 1;
+        const int npart_prev = (int)cdiv(m + 1, TRD_TC);  // tiles of the previous column's pass
+        hipLaunchKernelGGL(k_trd_col, dim3(1), dim3(1024), 0, st, H, N, (int)N, (int)j, d, e, tau, vbuf, qbuf,
+                           ppart, j > 0 ? npart_prev : 0, 0);
+        if (ok()) return GSYEIG_EHIP;
+        hipLaunchKernelGGL(k_trd_upd, dim3((unsigned)cdiv(m, 256), (unsigned)cdiv(m, TRD_TC)), dim3(256), 0, st, H,
+                           N, (int)N, (int)j, tau, vbuf, qbuf, ppart);
+        if (ok()) return GSYEIG_EHIP;
+    }
+    const int64_t jl = N >= 2 ? N - 2 : 0;
+    hipLaunchKernelGGL(k_trd_col, dim3(1), dim3(1024), 0, st, H, N, (int)N, (int)jl, d, e, tau, vbuf, qbuf, ppart,
+                       (int)cdiv(N - jl, TRD_TC), 1);
+    return ok();
 }
 
 // Eigenpairs of a symmetric N x N matrix H (column-major, ld N; destroyed):
 // the nwant smallest (which = 0) or largest (which = 1), ascending, into
 // w[0..nwant) (w[nwant] = the opposite extreme) and Q (N x nwant, ld N).
-int syev_small(int64_t N, double *H, int64_t nwant, int which, double *w, double *Q, double *scratch,
-               hipStream_t st)
+int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
+               double *scratch, hipStream_t st)
 {
     if (N < 1 || N > SYTRD_MAX || nwant < 1 || nwant > N) return GSYEIG_EHIP;
     double *d = scratch, *e = d + N, *tau = e + N, *tri = tau + N + 8;
-    hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(1024), 0, st, H, N, (int)N, d, e, tau);
-    if (ok()) return GSYEIG_EHIP;
+    double *aux = tri + 7 * N * nwant;
+    if (sytrd_launch(N, H, d, e, tau, aux, st)) return GSYEIG_EHIP;
     int rc = launch_tri_bisect(d, e, N, nwant, which, w, st);
     if (rc) return rc;
-    rc = launch_tri_vectors(d, e, N, nwant, w, Q, N, tri, 1, nullptr, st);
+    rc = launch_tri_vectors(d, e, N, nwant, w, Q, N, tri, ctx ? 0 : 1, nullptr, st);
     if (rc) return rc;
+    if (ctx) {
+        // independent inverse-iteration vectors are orthogonal to about
+        // u ||T|| / gap; Cholesky QR twice finishes them unless two are
+        // near-parallel (tight clusters), which takes the clustered path
+        int *info_d = (int *)ctx->dscal + 26;
+        int *h = (int *)ctx->host_pinned + 26;
+        RTRY_HIP(orthonormalise_cols(ctx, N, nwant, Q, N, info_d));
+        if (hipMemcpyAsync(h, info_d, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GSYEIG_EHIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return GSYEIG_EHIP;
+        if (*h != 0) {
+            rc = launch_tri_vectors(d, e, N, nwant, w, Q, N, tri, 1, nullptr, st);
+            if (rc) return rc;
+        }
+    }
     hipLaunchKernelGGL(k_ormtr, dim3((unsigned)nwant), dim3(256), 0, st, H, N, (int)N, tau, Q, N);
     return ok();
 }
 
 int64_t syev_small_max() { return SYTRD_MAX; }
 
+
 // X = U^-1 V (trans = 0) or U^-T V (trans = 1) for a block of k columns, U
-// upper triangular stored FP32 with its super-block inverses in sb (FP64,
-// [Uinv | Uinv^T | ...]); V (n x k, ldv) is destroyed.  Right-looking over
-// super-blocks: X_S = Uinv_SS V_S, then the rows not yet solved lose
-// U_{.,S} X_S -- FP32 MFMA products with FP32 accumulation.
-int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const double *sb, double *V,
-                       int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st)
+// upper triangular stored FP64 or FP32 (u_f32) with its super-block
+// inverses in sb (FP64, [Uinv | Uinv^T | ...]); V (n x k, ldv) is
+// destroyed.  Right-looking over super-blocks: X_S = Uinv_SS V_S, then the
+// rows not yet solved lose U_{.,S} X_S -- matrix-core products, FP32
+// (f32 = 1, FP32 accumulation) or FP64.
+int launch_trsm_sb(int trans, const void *U, int u_f32, int64_t ldu, int64_t n, const double *sb, double *V,
+                   int64_t ldv, double *X, int64_t ldx, int64_t k, int f32, hipStream_t st)
 {
     const int64_t SB = trsv_sb_rows();
     const int64_t nsb = cdiv(n, SB), blk = SB * SB;
     const double *Uinv = sb, *UinvT = sb + nsb * blk;
+    const size_t esz = u_f32 ? sizeof(float) : sizeof(double);
+    const char *Ub = (const char *)U;
     for (int64_t q = 0; q < nsb; ++q) {
         const int64_t S = trans ? q : nsb - 1 - q;
         const int64_t s0 = S * SB;
@@ -593,7 +766,7 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
         d.B = V + s0; d.ldb = ldv; d.b_layout = 0;
         d.C = X + s0; d.ldc = ldx; d.c_layout = 0;
         d.alpha = 1.0; d.beta = 0.0;
-        d.f32 = 1;
+        d.f32 = f32;
         int rc = launch_gemm(d, st);
         if (rc) return rc;
         GemmDesc u{};
@@ -601,24 +774,30 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
         u.B = X + s0; u.ldb = ldx; u.b_layout = 0;
         u.ldc = ldv; u.c_layout = 0;
         u.alpha = -1.0; u.beta = 1.0;
-        u.a_f32 = 1; u.f32 = 1;
+        u.a_f32 = u_f32; u.f32 = f32;
         u.lda = ldu;
         if (!trans) {
             if (S == 0) continue;
             u.m = s0;
-            u.A = U + s0; u.a_layout = 1;                 // A(i, t) = U[i, s0 + t]
+            u.A = Ub + esz * (size_t)s0; u.a_layout = 1;                  // A(i, t) = U[i, s0 + t]
             u.C = V;
         } else {
             const int64_t s1 = s0 + r;
             if (s1 >= n) continue;
             u.m = n - s1;
-            u.A = U + s0 * ldu + s1; u.a_layout = 0;      // A(i, t) = U[s0 + t, s1 + i]
+            u.A = Ub + esz * (size_t)(s0 * ldu + s1); u.a_layout = 0;     // A(i, t) = U[s0 + t, s1 + i]
             u.C = V + s1;
         }
         rc = launch_gemm(u, st);
         if (rc) return rc;
     }
     return 0;
+}
+
+int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const double *sb, double *V,
+                       int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st)
+{
+    return launch_trsm_sb(trans, U, 1, ldu, n, sb, V, ldv, X, ldx, k, 1, st);
 }
 
 // ------------------------------------------------------------ refinement
@@ -725,7 +904,7 @@ int svqb(Ctx &c, int z, int64_t c0, int64_t r, double drop, int64_t *kept)
     RTRY(ok());
     hipLaunchKernelGGL(k_gram_apply, dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, st, b.C1, r, b.dsc);
     RTRY(ok());
-    RTRY(syev_small(r, b.C1, r, 0, b.theta, b.Qc, b.sy, st));
+    RTRY(syev_small(c.ctx, r, b.C1, r, 0, b.theta, b.Qc, b.sy, st));
     std::vector<double> sig((size_t)r);
     HIP_TRY(hipMemcpyAsync(sig.data(), b.theta, sizeof(double) * (size_t)r, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -757,7 +936,7 @@ int rayleigh_ritz(Ctx &c, int z, int64_t N, int64_t nk, int which, int *znew)
     RTRY(gemm_tn(b.Z[z], b.ldr, b.AZ[z], b.ldr, c.n, N, N, b.H, N, 1.0, 0.0, b.part, b.part_elems, st));
     hipLaunchKernelGGL(k_symmetrise, dim3((unsigned)cdiv(N * N, 256)), dim3(256), 0, st, b.H, N, N);
     RTRY(ok());
-    RTRY(syev_small(N, b.H, nk, which, b.theta, b.Qc, b.sy, st));
+    RTRY(syev_small(c.ctx, N, b.H, nk, which, b.theta, b.Qc, b.sy, st));
     const int oz = 1 - z;
     RTRY(gemm_nn(b.Z[z], b.ldr, b.Qc, N, c.n, N, nk, b.Z[oz], b.ldr, 1.0, 0.0, st));
     RTRY(gemm_nn(b.AZ[z], b.ldr, b.Qc, N, c.n, N, nk, b.AZ[oz], b.ldr, 1.0, 0.0, st));

@@ -199,6 +199,8 @@ def _syev_case(name, N):
     (1, 1, 0, "random"), (2, 2, 0, "random"), (3, 1, 1, "random"), (17, 9, 0, "random"),
     (64, 64, 0, "random"), (200, 50, 1, "random"), (513, 300, 0, "random"),
     (40, 40, 0, "identity"), (96, 96, 0, "repeated"), (250, 125, 0, "clustered"), (500, 250, 0, "clustered"),
+    # orders above 192 take the whole-GPU reduction (two launches per column)
+    (300, 300, 0, "identity"), (260, 260, 0, "repeated"), (1500, 400, 0, "random"), (1200, 600, 1, "clustered"),
 ])
 def test_syev_small(gs, ctx, torch, orc, N, nwant, which, name):
     say("syev_small", N, nwant, which, name)
