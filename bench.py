@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--basis", type=int, default=0, help="--config 3: basis size before a restart (0 = auto)")
     ap.add_argument("--acc32", type=int, default=0, help="--config 3: 1 = FP32 accumulation in block products")
     ap.add_argument("--no-fem", action="store_true", help="--config 3: skip the FEM pencil")
+    ap.add_argument("--fem-only", action="store_true", help="--config 3: only the FEM pencil")
+    ap.add_argument("--fem-prec", type=int, default=1, help="--config 3: FEM pencil precision (0 FP64, 1 mixed)")
+    ap.add_argument("--eta-tol", type=float, default=0.0, help="refinement target (0 = library default)")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -265,10 +268,17 @@ def bench_block(args, cfg):
     blk = args.block or cfg["block"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"generating n={n} s={s} law={cfg['law']} (device draws)")
+    if args.fem_only:
+        return bench_fem(args, cfg, blk)
     t0 = time.perf_counter()
-    inst = gen.known_spectrum_device(n, cfg["law"], seed=gen.BASE_SEED + 3, stream=(3, 0, 0), device=dev,
-                                     keep_factors=False, rng_kind="torch")
+    if n * n >= 2**31:  # row-blocked assembly with Y = I - 2 Q Q^T (no dense n x n QR)
+        log(f"generating n={n} s={s} law={cfg['law']} (device draws, row-blocked, Y = I - 2QQ^T)")
+        inst = gen.known_spectrum_device_blocked(n, cfg["law"], seed=gen.BASE_SEED + 3, stream=(3, 0, 0),
+                                                 device=dev)
+    else:
+        log(f"generating n={n} s={s} law={cfg['law']} (device draws)")
+        inst = gen.known_spectrum_device(n, cfg["law"], seed=gen.BASE_SEED + 3, stream=(3, 0, 0), device=dev,
+                                         keep_factors=False, rng_kind="torch")
     A, B0 = inst["A"], inst["B"]
     lam_true = np.sort(inst["lam"])[:s]
     B = torch.empty_like(B0)
@@ -286,13 +296,15 @@ def bench_block(args, cfg):
         o.basis = args.basis
         o.block_acc32 = args.acc32
         o.profile_every = args.profile_every
+        if args.eta_tol > 0:
+            o.eta_tol = args.eta_tol
         for k, v in kw.items():
             setattr(o, k, v)
         return o
 
     def run(Am, Bm, Bsrc, o):
         if Bsrc is not None:
-            Bm.copy_(Bsrc)
+            gen.copy_rows(Bm, Bsrc)
         torch.cuda.synchronize()
         t = time.perf_counter()
         rc, info = gs.gsyeig_solve(solver.ctx, n, s, Am, n, Bm, n, o, Lam, X, n)
@@ -335,17 +347,8 @@ def bench_block(args, cfg):
     peak = 157.3 if args.acc32 else 78.6
     del A, B, B0, inst
     torch.cuda.empty_cache()
-    fem = None
-    if not args.no_fem:
-        K, M = gen.fem_pencil_device(n, dev)
-        lam_ref, _ = gen.fem_eigs(n, s)
-        dtf, inff = run(K, M, None, opts(invert=1))
-        show("fem (inverse pencil)", dtf, inff)
-        lam_f = Lam.cpu().numpy()
-        fem = {"time_s": dtf, "operator_applications": int(inff.steps), "restarts": int(inff.restarts),
-               "max_rel_err_vs_closed_form": float(np.max(np.abs(lam_f - lam_ref) / lam_ref)),
-               "eta_max": inff.eta_max, "omega": inff.omega}
-        del K, M
+    solver.close()
+    fem = None if args.no_fem else bench_fem(args, cfg, blk, emit=False)
     out = {
         "metric": "time-to-s-eigenpairs", "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak",
@@ -370,6 +373,57 @@ def bench_block(args, cfg):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, cfg["law"])
     print(json.dumps(out), flush=True)
+
+
+def bench_fem(args, cfg, blk, emit=True):
+    """The 1-D FEM pencil (stiffness, mass) of order n through the inverse
+    pencil with block Lanczos, against its closed-form eigenvalues."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1111_6374_amd as gs
+
+    n, s = cfg["n"], cfg["s"]
+    dev = torch.device("cuda:0")
+    K, M = gen.fem_pencil_device(n, dev)
+    lam_ref, _ = gen.fem_eigs(n, s)
+    o = gs.gsyeig_opts_default()
+    o.prec = args.fem_prec
+    o.block = blk
+    o.basis = args.basis
+    o.block_acc32 = args.acc32
+    o.invert = 1
+    if args.eta_tol > 0:
+        o.eta_tol = args.eta_tol
+    Lam = torch.empty(s, dtype=torch.float64, device=dev)
+    X = torch.empty(s, n, dtype=torch.float64, device=dev)
+    with gs.Solver() as sv:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, inf = gs.gsyeig_solve(sv.ctx, n, s, K, n, M, n, o, Lam, X, n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+    if rc:
+        raise gs.GsyeigError("gsyeig_solve", rc)
+    lam = Lam.cpu().numpy()
+    rel = np.abs(lam - lam_ref) / lam_ref
+    j = int(np.argmax(rel))
+    # the same errors as seen by the inverse pencil: |d mu| / ||C||, mu = 1/lambda
+    dmu = np.abs(1.0 / lam - 1.0 / lam_ref) * lam_ref[0]
+    log(f"fem (inverse pencil, prec {args.fem_prec}): {dt:.2f} s (GS1 {inf.t_gs1_ms:.0f} ms, KI {inf.t_ki_ms:.0f} "
+        f"[projected solves {inf.t_rr_ms:.0f} in {inf.rr_count}], refine {inf.t_refine_ms:.0f}, check "
+        f"{inf.t_check_ms:.0f}) ops={inf.steps} max rel err {rel[j]:.2e} at mode {j + 1} "
+        f"(rel err mode 1 {rel[0]:.2e}, mode {s} {rel[-1]:.2e}), max |dmu|/||C|| {dmu.max():.2e}, "
+        f"eta={inf.eta_max:.2e} rounds={inf.refine_iters}")
+    out = {"time_s": dt, "prec": "mixed" if args.fem_prec else "fp64", "operator_applications": int(inf.steps),
+           "restarts": int(inf.restarts), "max_rel_err_vs_closed_form": float(rel[j]), "worst_mode": j + 1,
+           "max_abs_dmu_over_normC": float(dmu.max()), "eta_max": inf.eta_max, "omega": inf.omega,
+           "refine_rounds": int(inf.refine_iters)}
+    del K, M
+    if emit:
+        print(json.dumps({"fem_inverse_pencil": out, "n": n, "s": s, "block": blk}), flush=True)
+    return out
 
 
 def bench_mixed(args, cfg):

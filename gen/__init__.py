@@ -147,6 +147,88 @@ def known_spectrum_device(n: int, law: str = "spaced", seed: int = BASE_SEED, st
     return out
 
 
+def _row_blocks(n: int, nb: int):
+    return [(r0, min(n, r0 + nb)) for r0 in range(0, n, nb)]
+
+
+def known_spectrum_device_blocked(n: int, law: str = "spaced", seed: int = BASE_SEED, stream=(0,),
+                                  device="cuda", nb: int = 4096, rank: int = 256):
+    """Known-spectrum pencil for n beyond what single-tensor device kernels
+    and a dense QR handle (n^2 > 2^31): A = U^T Y diag(lam) Y^T U, B = U^T U
+    with the same U and lam laws as ``known_spectrum``, and the orthogonal
+    Y = I - 2 Q Q^T, Q the orthonormal factor of a seeded Gaussian n x rank
+    (an exactly orthogonal similarity, so lam is exact; A and B are dense).
+    Every device operation touches contiguous row blocks of at most nb rows.
+    Draws come from a torch generator seeded with (seed, stream)."""
+    import torch
+
+    f64 = torch.float64
+    tg = torch.Generator(device=device)
+    tg.manual_seed(int(np.random.SeedSequence([int(seed)] + [int(v) for v in stream]).generate_state(1)[0]))
+    blocks = _row_blocks(n, nb)
+    U = torch.empty(n, n, dtype=f64, device=device)
+    for r0, r1 in blocks:
+        blk = torch.randn(r1 - r0, n, generator=tg, device=device, dtype=f64) / math.sqrt(n)
+        blk = torch.triu(blk, diagonal=r0 + 1)
+        i = torch.arange(r1 - r0, device=device)
+        blk[i, r0 + i] = 1.0 + torch.rand(r1 - r0, generator=tg, device=device, dtype=f64)
+        U[r0:r1].copy_(blk)
+        del blk
+    Q, _ = torch.linalg.qr(torch.randn(n, rank, generator=tg, device=device, dtype=f64))
+    lam_h = SPECTRA[law](n, rng(seed, *stream))
+    lam = torch.from_numpy(lam_h).to(device)
+    # M = Y diag(lam) Y = diag(lam) + L R^T with L = [Q, P, Q S], R = [-2P, -2Q, 4Q],
+    # P = diag(lam) Q, S = Q^T P
+    P = lam[:, None] * Q
+    S = Q.t() @ P
+    L = torch.cat([Q, P, Q @ S], dim=1)
+    Rt = torch.cat([-2.0 * P, -2.0 * Q, 4.0 * Q], dim=1).t().contiguous()
+    del P, S
+    M = torch.empty(n, n, dtype=f64, device=device)
+    for r0, r1 in blocks:
+        M[r0:r1] = L[r0:r1] @ Rt
+        M[r0:r1].diagonal(r0).add_(lam[r0:r1])
+    del L, Rt, Q
+    # T = M U (U's block (k, c) vanishes for c < k)
+    T = torch.zeros(n, n, dtype=f64, device=device)
+    for r0, r1 in blocks:
+        Tr = T[r0:r1]
+        for k0, k1 in blocks:
+            Tr[:, k0:].addmm_(M[r0:r1, k0:k1], U[k0:k1, k0:])
+    del M
+
+    def ut_times(X):
+        """U^T X by row blocks (U's block (k, r) vanishes for k > r)."""
+        out = torch.zeros(n, n, dtype=f64, device=device)
+        for r0, r1 in blocks:
+            Or = out[r0:r1]
+            for k0, k1 in blocks:
+                if k0 > r0:
+                    break
+                Or.addmm_(U[k0:k1, r0:r1].t(), X[k0:k1])
+        return out
+
+    def symmetrise(X):
+        for a, (r0, r1) in enumerate(blocks):
+            for c0, c1 in blocks[a:]:
+                v = 0.5 * (X[r0:r1, c0:c1] + X[c0:c1, r0:r1].t())
+                X[r0:r1, c0:c1] = v
+                X[c0:c1, r0:r1] = v.t()
+        return X
+
+    A = symmetrise(ut_times(T))
+    del T
+    B = symmetrise(ut_times(U))
+    del U
+    return {"A": A, "B": B, "lam": lam_h}
+
+
+def copy_rows(dst, src, nb: int = 4096):
+    """dst[:] = src for large n x n device tensors, one row block at a time."""
+    for r0, r1 in _row_blocks(src.shape[0], nb):
+        dst[r0:r1].copy_(src[r0:r1])
+
+
 # --------------------------------------------------------------------------
 # the 1-D finite-element pencil
 # --------------------------------------------------------------------------
@@ -164,18 +246,20 @@ def fem_pencil(n: int):
     return K, M
 
 
-def fem_pencil_device(n: int, device="cuda"):
+def fem_pencil_device(n: int, device="cuda", nb: int = 4096):
     """``fem_pencil(n)`` assembled directly on a torch device (same values)."""
     import torch
 
     h = 1.0 / (n + 1)
-    K = torch.zeros(n, n, dtype=torch.float64, device=device)
-    M = torch.zeros(n, n, dtype=torch.float64, device=device)
-    K.diagonal().fill_(2.0 / h)
-    M.diagonal().fill_(4.0 * h / 6.0)
-    for off in (1, -1):
-        K.diagonal(off).fill_(-1.0 / h)
-        M.diagonal(off).fill_(h / 6.0)
+    K = torch.empty(n, n, dtype=torch.float64, device=device)
+    M = torch.empty(n, n, dtype=torch.float64, device=device)
+    for r0, r1 in _row_blocks(n, nb):  # row blocks: every kernel sees < 2^31 elements
+        for X, dv, ov in ((K, 2.0 / h, -1.0 / h), (M, 4.0 * h / 6.0, h / 6.0)):
+            Xr = X[r0:r1]
+            Xr.zero_()
+            Xr.diagonal(r0).fill_(dv)
+            Xr.diagonal(r0 + 1).fill_(ov)   # (i, r0 + i + 1): super-diagonal
+            Xr.diagonal(r0 - 1).fill_(ov)   # (i, r0 + i - 1): sub-diagonal
     return K, M
 
 
@@ -185,11 +269,13 @@ def fem_eigs(n: int, s: int):
     lam_j = (6/h^2) (1 - cos(j pi h)) / (2 + cos(j pi h)),
     x_j[k] = sqrt(6 / (2 + cos(j pi h))) sin(j (k+1) pi h) (M-normalised),
     j = 1..s, ascending.  Returns (lam (s,), X (s, n) with row j-1 = x_j).
+    1 - cos(t) is evaluated as 2 sin^2(t/2): for small j pi h the difference
+    would cancel most digits (about 9 at n = 65536).
     """
     h = 1.0 / (n + 1)
     j = np.arange(1, s + 1, dtype=np.float64)
     c = np.cos(j * math.pi * h)
-    lam = (6.0 / h**2) * (1.0 - c) / (2.0 + c)
+    lam = (6.0 / h**2) * (2.0 * np.sin(0.5 * j * math.pi * h) ** 2) / (2.0 + c)
     k = np.arange(1, n + 1, dtype=np.float64)
     X = np.sqrt(6.0 / (2.0 + c))[:, None] * np.sin(np.outer(j, k) * math.pi * h)
     return lam, X

@@ -300,8 +300,13 @@ int block_apply(gsyeig_ctx *ctx, const BlkOp &op, int64_t n, const double *X, in
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], st));
-    TRY(launch_blk_copy(X, ldx, w.t1, ldw, n, b, st));
-    TRY(launch_trsm_sb(0, op.U, op.u_f32, op.ldu, n, op.sb, w.t1, ldw, w.t2, ldw, b, op.f32, st));
+    if (op.W) {
+        TRY(launch_trsm_w(0, op.W, op.w_f32, op.ldw, n, op.sb, const_cast<double *>(X), ldx, w.t2, ldw, b, op.f32,
+                          st));
+    } else {
+        TRY(launch_blk_copy(X, ldx, w.t1, ldw, n, b, st));
+        TRY(launch_trsm_sb(0, op.U, op.u_f32, op.ldu, n, op.sb, w.t1, ldw, w.t2, ldw, b, op.f32, st));
+    }
     if (sample) HIP_TRY(hipEventRecord(e[1], st));
     GemmDesc d{};
     d.m = n; d.n = b; d.k = n;
@@ -312,7 +317,10 @@ int block_apply(gsyeig_ctx *ctx, const BlkOp &op, int64_t n, const double *X, in
     d.f32 = op.f32;
     TRY(launch_gemm(d, st));
     if (sample) HIP_TRY(hipEventRecord(e[2], st));
-    TRY(launch_trsm_sb(1, op.U, op.u_f32, op.ldu, n, op.sb, w.t1, ldw, Y, ldy, b, op.f32, st));
+    if (op.W)
+        TRY(launch_trsm_w(1, op.W, op.w_f32, op.ldw, n, op.sb, w.t1, ldw, Y, ldy, b, op.f32, st));
+    else
+        TRY(launch_trsm_sb(1, op.U, op.u_f32, op.ldu, n, op.sb, w.t1, ldw, Y, ldy, b, op.f32, st));
     if (sample) {
         HIP_TRY(hipEventRecord(e[3], st));
         ctx->npev += 4;

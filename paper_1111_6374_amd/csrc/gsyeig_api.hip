@@ -271,7 +271,7 @@ static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double
 // on inverse-iteration eigenvectors of T_m, whose mutual overlaps are tiny
 // except inside clusters of close eigenvalues; there any orthonormal basis
 // of the computed vectors is as good.  *info_d != 0 if G was not positive
-// definite or if two columns overlapped by more than 1e-8 (the caller then
+// definite or if two columns overlapped by more than 1e-4 (the caller then
 // falls back to sequential Gram-Schmidt with extra inverse-iteration solves).
 int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d)
 {
@@ -293,9 +293,11 @@ int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64
         g.alpha = 1.0; g.beta = 0.0;
         g.splitk = (int)sk; g.part = part;
         TRY(launch_gemm(g, ctx->stream));
-        // overlaps beyond 1e-8 mean near-equal Ritz values whose vectors need
-        // the sequential treatment (extra solves inside the cluster)
-        if (pass == 0) TRY(launch_flag_offdiag(G, nw, 1e-8, info_d, ctx->stream));
+        // overlaps beyond 1e-4 mean near-equal Ritz values whose independent
+        // inverse-iteration vectors may be near-parallel: those need the
+        // sequential treatment (extra solves inside the cluster).  Smaller
+        // overlaps (about u ||T|| / gap) are removed by the two passes.
+        if (pass == 0) TRY(launch_flag_offdiag(G, nw, 1e-4, info_d, ctx->stream));
         TRY(potrf_core(ctx, nw, G, nw, Dv, info2));
         TRY(launch_accum_info(info2, info_d, ctx->stream));
         // Ri = R^-1 (column-major; R is G's upper triangle, row-major)
@@ -680,7 +682,7 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
     TRY(potrf_mixed_enqueue(ctx, n, B, ldb, U32, ld32, Dinv, info_d));
     LzOp op;
-    TRY(mixed_operator(ctx, n, A, lda, U32, ld32, true, &op, o.block == 1));
+    TRY(mixed_operator(ctx, n, A, lda, U32, ld32, true, &op));
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
     int *hi = (int *)ctx->host_pinned;
     HIP_TRY(hipMemcpyAsync(hi, info_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -695,7 +697,7 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     LzResult r{};
     BlzResult br{};
     if (o.block > 1) {
-        BlkOp bop{U32, 1, ld32, op.sb, op.A32, 1, ld32, o.block_acc32 ? 1 : 0};
+        BlkOp bop{U32, 1, ld32, op.W32, 1, op.ldw32, op.sb, op.A32, 1, ld32, o.block_acc32 ? 1 : 0};
         TRY(blz_solve(ctx, n, s, k, bop, &o, theta_k, Y, ldy, &br));
         r.steps = br.steps;
         r.nconv = br.nconv;
@@ -1067,7 +1069,8 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
     if (o.block > 1) {
         const double *sb;
         TRY(block_sb_fp64(ctx, n, U, ldu, Dinv, &sb));
-        BlkOp bop{U, 0, ldu, sb, A, 0, lda, 0};
+        const double *Wd = (ctx->trsv_block == 64) ? nullptr : (const double *)ctx->ws[WS_W];
+        BlkOp bop{U, 0, ldu, Wd, 0, round_ld(n), sb, A, 0, lda, 0};
         BlzResult br{};
         TRY(blz_solve(ctx, n, s, s, bop, &o, theta, Y, ldy, &br));
         if (steps_out) *steps_out = br.steps;
@@ -1166,7 +1169,8 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (o.block > 1) {
         const double *sb;
         TRY(block_sb_fp64(ctx, n, B, ldb, Dinv, &sb));
-        BlkOp bop{B, 0, ldb, sb, A, 0, lda, 0};
+        const double *Wd = (ctx->trsv_block == 64) ? nullptr : (const double *)ctx->ws[WS_W];
+        BlkOp bop{B, 0, ldb, Wd, 0, round_ld(n), sb, A, 0, lda, 0};
         TRY(blz_solve(ctx, n, s, s, bop, &o, Lambda, X, ldx, &br));
         r.steps = br.steps;
         r.nconv = br.nconv;

@@ -116,6 +116,8 @@ struct GemmDesc {
     int f32;                  // FP32 compute (MFMA f32, FP32 accumulation); else FP64
     int splitk;               // > 1: split K into chunks summed through `part`
     double *part;             // split-K scratch: gemm_splitk_parts(d) * m * n doubles
+    int64_t batch;            // > 1: that many products, operands advanced by the strides
+    int64_t stride_a, stride_b, stride_c;  // elements between consecutive products
 };
 int launch_gemm(const GemmDesc &d, hipStream_t st);
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
@@ -225,6 +227,11 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
                        int64_t ldv, double *X, int64_t ldx, int64_t k, hipStream_t st);
 int launch_trsm_sb(int trans, const void *U, int u_f32, int64_t ldu, int64_t n, const double *sb, double *V,
                    int64_t ldv, double *X, int64_t ldx, int64_t k, int f32, hipStream_t st);
+// The same on U = D (I + W) (W from launch_make_w / _f32, FP64 or FP32): the
+// diagonal super-blocks as one batched product, the chain only the
+// off-diagonal updates.  trans = 0 keeps V; trans = 1 destroys it.
+int launch_trsm_w(int trans, const void *W, int w_f32, int64_t ldw, int64_t n, const double *sb, double *V,
+                  int64_t ldv, double *X, int64_t ldx, int64_t k, int f32, hipStream_t st);
 int launch_blk_copy(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, int64_t k,
                     hipStream_t st);
 int launch_identity(double *X, int64_t ld, int64_t r, hipStream_t st);
@@ -240,13 +247,14 @@ int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, 
                double *scratch, hipStream_t st);
 // Cholesky QR twice on the nw columns of S (m x nw, column-major); *info_d
 // != 0 when the Gram matrix was not positive definite or two columns
-// overlapped by more than 1e-8 (two device ints)
+// overlapped by more than 1e-4 (two device ints)
 int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d);
 int64_t syev_small_max();
 
 // block Lanczos with thick restart (blz.hip)
 struct BlkOp {             // C = U^-T A U^-1 on blocks (TRSM, SYMM on the matrix cores)
     const void *U; int u_f32; int64_t ldu;
+    const void *W; int w_f32; int64_t ldw;   // U = D (I + W) when W != NULL (then U is not read)
     const double *sb;      // super-block inverses of U (FP64)
     const void *A; int a_f32; int64_t lda;
     int f32;               // FP32 products with FP32 accumulation (else FP64)

@@ -19,6 +19,8 @@
 // current one is multiplied.  With split-K, blockIdx.z owns one K chunk and
 // writes its partial tile to scratch; a second kernel adds the chunks in a
 // fixed order (reproducible) and applies alpha/beta.
+#include <stdint.h>
+
 #include "internal.h"
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -175,6 +177,192 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
             }
 }
 
+// ---------------------------------------------------------------- skinny
+// C (m x n, column-major FP64) = alpha A B + beta C for n <= 32 columns: the
+// shapes of the block operator (n rows times a block of b = 16 or 32
+// columns; K = n for the symmetric product, 512 for the super-block
+// updates).  One 256-thread workgroup owns 128 rows and all BN columns, so
+// every element of A is read once.  K is staged through LDS in slabs of
+// 32 KB of A (64 FP32 or 32 FP64 values deep), A kept in its storage type
+// and converted as it enters the matrix cores; the next slab is loaded into
+// registers with 16-byte vector loads while the current one is multiplied.
+// Tiles that overhang m or K (and unaligned operands) load element-wise.
+// A is FP64 or FP32, column- (AL = 0) or row-major (AL = 1); B is FP64
+// column-major.
+constexpr int SK_TM = 128;
+
+struct SkArgs {
+    int64_t m, n, k;
+    const void *A; int64_t lda;
+    const double *B; int64_t ldb;
+    double *C; int64_t ldc;
+    double alpha, beta;
+    int vec;   // operands aligned for 16-byte loads
+    int64_t sa, sb, sc;   // batch strides (elements); blockIdx.y = product
+};
+
+template <typename TC, typename TA, int AL, int BN>
+__global__ __launch_bounds__(256) void k_gemm_skinny(SkArgs g)
+{
+    using V4 = typename Acc<TC>::type;
+    constexpr int TK = 128 / (int)sizeof(TA) * 2;   // 64 (FP32 A) or 32 (FP64 A)
+    constexpr int VA = 16 / (int)sizeof(TA);        // A values per 16-byte load
+    constexpr int NA = SK_TM * TK / 256;            // A values per thread per slab (32 or 16)
+    constexpr int NAV = NA / VA;                    // 16-byte loads of A per thread (8)
+    constexpr int NBV = TK * BN / 256;               // B values per thread per slab
+    constexpr int PADA = (sizeof(TA) == 8) ? 2 : 4;
+    constexpr int NBLK = BN / 16;
+    const TA *Ap = (const TA *)g.A + (int64_t)blockIdx.y * g.sa;
+    g.B += (int64_t)blockIdx.y * g.sb;
+    g.C += (int64_t)blockIdx.y * g.sc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tm0 = (int64_t)blockIdx.x * SK_TM;
+    __shared__ TA As[TK][SK_TM + PADA];
+    __shared__ TC Bs[TK][BN + 2];
+
+    // A: vector v of thread t covers VA consecutive values along A's
+    // contiguous index.  AL = 1 (row-major): row ii, k kk..kk+VA-1;
+    // AL = 0 (column-major): k kk, rows ii..ii+VA-1.
+    auto a_pos = [&](int v, int &ii, int &kk) {
+        if constexpr (AL == 1) {
+            constexpr int PR = TK / VA;                 // vectors per row
+            const int e = tid + 256 * v;
+            ii = e / PR;
+            kk = (e % PR) * VA;
+        } else {
+            constexpr int PC = SK_TM / VA;              // vectors per column
+            const int e = tid + 256 * v;
+            kk = e / PC;
+            ii = (e % PC) * VA;
+        }
+    };
+    // B: thread t covers NBV consecutive k of column jb
+    constexpr int BPC = TK / NBV;                        // threads per column
+    const int jb = tid / BPC, kb = (tid % BPC) * NBV;
+
+    TA ra[NA];
+    TC rb[NBV];
+    auto fetch = [&](int64_t k0) {
+        const bool full = g.vec && tm0 + SK_TM <= g.m && k0 + TK <= g.k;
+#pragma unroll
+        for (int v = 0; v < NAV; ++v) {
+            int ii, kk;
+            a_pos(v, ii, kk);
+            const int64_t gi = tm0 + ii, gk = k0 + kk;
+            const TA *src = (AL == 1) ? Ap + gi * g.lda + gk : Ap + gk * g.lda + gi;
+            if (full) {
+                if constexpr (sizeof(TA) == 4) {
+                    const float4 q = *(const float4 *)src;
+                    ra[v * 4 + 0] = q.x; ra[v * 4 + 1] = q.y; ra[v * 4 + 2] = q.z; ra[v * 4 + 3] = q.w;
+                } else {
+                    const double2 q = *(const double2 *)src;
+                    ra[v * 2 + 0] = q.x; ra[v * 2 + 1] = q.y;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < VA; ++u) {
+                    const int64_t ei = gi + ((AL == 1) ? 0 : u), ek = gk + ((AL == 1) ? u : 0);
+                    ra[v * VA + u] = (ei < g.m && ek < g.k) ? Ap[(AL == 1) ? ei * g.lda + ek : ek * g.lda + ei]
+                                                            : (TA)0;
+                }
+            }
+        }
+        const bool bfull = g.vec && k0 + TK <= g.k && jb < g.n;
+        const double *bsrc = g.B + (int64_t)jb * g.ldb + k0 + kb;
+        if (bfull) {
+#pragma unroll
+            for (int u = 0; u < NBV; u += 2) {
+                const double2 q = *(const double2 *)(bsrc + u);
+                rb[u] = (TC)q.x;
+                rb[u + 1] = (TC)q.y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NBV; ++u)
+                rb[u] = (jb < g.n && k0 + kb + u < g.k) ? (TC)bsrc[u] : (TC)0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int v = 0; v < NAV; ++v) {
+            int ii, kk;
+            a_pos(v, ii, kk);
+#pragma unroll
+            for (int u = 0; u < VA; ++u) {
+                if constexpr (AL == 1) As[kk + u][ii] = ra[v * VA + u];
+                else As[kk][ii + u] = ra[v * VA + u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NBV; ++u) Bs[kb + u][jb] = rb[u];
+    };
+
+    V4 acc[2][NBLK];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) acc[a][b] = V4{0, 0, 0, 0};
+    const int li = lane & 15, lk = lane >> 4;
+    if (g.k > 0) fetch(0);
+    for (int64_t k0 = 0; k0 < g.k; k0 += TK) {
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if (k0 + TK < g.k) fetch(k0 + TK);
+#pragma unroll
+        for (int kq = 0; kq < TK / 4; ++kq) {
+            const int kr = kq * 4 + lk;
+            TC av[2], bv[NBLK];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = (TC)As[kr][wave * 32 + a * 16 + li];
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) bv[b] = Bs[kr][b * 16 + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < NBLK; ++b) {
+                    if constexpr (sizeof(TC) == 8)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                    else
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+                }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = tm0 + wave * 32 + a * 16 + d_row<TC>(lk, r);
+                const int64_t j = b * 16 + li;
+                if (i >= g.m || j >= g.n) continue;
+                double *cp = &g.C[j * g.ldc + i];
+                double v = g.alpha * (double)acc[a][b][r];
+                if (g.beta != 0.0) v += g.beta * *cp;
+                *cp = v;
+            }
+}
+
+template <typename TC, typename TA, int AL>
+int run_skinny_bn(const SkArgs &a, int64_t batch, hipStream_t st)
+{
+    dim3 grid((unsigned)cdiv(a.m, SK_TM), (unsigned)batch);
+    if (a.n <= 16) hipLaunchKernelGGL((k_gemm_skinny<TC, TA, AL, 16>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm_skinny<TC, TA, AL, 32>), grid, dim3(256), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+template <typename TC>
+int run_skinny(SkArgs a, int a_f32, int al, int64_t batch, hipStream_t st)
+{
+    const int64_t va = a_f32 ? 4 : 2;
+    a.vec = ((uintptr_t)a.A % 16 == 0) && (a.lda % va == 0) && ((uintptr_t)a.B % 16 == 0) && (a.ldb % 2 == 0) &&
+            (batch == 1 || (a.sa % va == 0 && a.sb % 2 == 0));
+    if (a_f32) return al ? run_skinny_bn<TC, float, 1>(a, batch, st) : run_skinny_bn<TC, float, 0>(a, batch, st);
+    return al ? run_skinny_bn<TC, double, 1>(a, batch, st) : run_skinny_bn<TC, double, 0>(a, batch, st);
+}
+
 template <typename TCS>
 __global__ void k_splitk_reduce(const double *__restrict__ part, int nz, int64_t m, int64_t n, void *C,
                                 int64_t ldc, int c_row, double alpha, double beta, int upper_only)
@@ -234,6 +422,28 @@ int launch_gemm(const GemmDesc &d, hipStream_t st)
 {
     if (d.m <= 0 || d.n <= 0) return 0;
     if (d.a_layout == 2 && d.a_f32) return GSYEIG_EHIP;
+    const int64_t batch = d.batch > 1 ? d.batch : 1;
+    // a block of at most 32 FP64 columns times a tall A: the skinny kernel
+    if (d.n <= 32 && d.m >= SK_TM && d.a_layout != 2 && !d.b_f32 && !d.c_f32 && d.b_layout == 0 &&
+        d.c_layout == 0 && !d.upper_only && d.splitk <= 1) {
+        SkArgs a{d.m, d.n, d.k > 0 ? d.k : 0, d.A, d.lda, (const double *)d.B, d.ldb, (double *)d.C, d.ldc,
+                 d.alpha, d.beta, 0, d.stride_a, d.stride_b, d.stride_c};
+        return d.f32 ? run_skinny<float>(a, d.a_f32, d.a_layout, batch, st)
+                     : run_skinny<double>(a, d.a_f32, d.a_layout, batch, st);
+    }
+    if (batch > 1) {  // other shapes: one launch per product
+        GemmDesc e = d;
+        e.batch = 1;
+        const size_t ea = d.a_f32 ? 4 : 8, eb = d.b_f32 ? 4 : 8, ec = d.c_f32 ? 4 : 8;
+        for (int64_t q = 0; q < batch; ++q) {
+            e.A = (const char *)d.A + ea * (size_t)(q * d.stride_a);
+            e.B = (const char *)d.B + eb * (size_t)(q * d.stride_b);
+            e.C = (char *)d.C + ec * (size_t)(q * d.stride_c);
+            const int rc = launch_gemm(e, st);
+            if (rc) return rc;
+        }
+        return 0;
+    }
     Args a{d.m, d.n, d.k > 0 ? d.k : 0, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.c_layout == 1,
            d.alpha, d.beta, d.a_diag, d.upper_only, 0, nullptr};
     int nz = 1;

@@ -800,6 +800,80 @@ int launch_trsm_sb_f32(int trans, const float *U, int64_t ldu, int64_t n, const 
     return launch_trsm_sb(trans, U, 1, ldu, n, sb, V, ldv, X, ldx, k, 1, st);
 }
 
+// Y_S = D_SS Z_S for every super-block S (D = Uinv or Uinv^T blocks, FP64
+// row-major SB x SB): one batched product for the full super-blocks, one for
+// a ragged last one
+static int sb_diag_products(const double *D, const double *Z, int64_t ldz, double *Y, int64_t ldy, int64_t n,
+                            int64_t k, int f32, hipStream_t st)
+{
+    const int64_t SB = trsv_sb_rows();
+    const int64_t nsb = cdiv(n, SB), nfull = n / SB, blk = SB * SB;
+    GemmDesc d{};
+    d.n = k;
+    d.lda = SB; d.a_layout = 1;
+    d.ldb = ldz; d.b_layout = 0;
+    d.ldc = ldy; d.c_layout = 0;
+    d.alpha = 1.0; d.beta = 0.0;
+    d.f32 = f32;
+    if (nfull > 0) {
+        d.m = SB; d.k = SB;
+        d.A = D; d.B = Z; d.C = Y;
+        d.batch = nfull;
+        d.stride_a = blk; d.stride_b = SB; d.stride_c = SB;
+        int rc = launch_gemm(d, st);
+        if (rc) return rc;
+    }
+    if (nsb > nfull) {
+        const int64_t s0 = nfull * SB;
+        d.m = n - s0; d.k = n - s0;
+        d.A = D + nfull * blk; d.B = Z + s0; d.C = Y + s0;
+        d.batch = 1;
+        return launch_gemm(d, st);
+    }
+    return 0;
+}
+
+int launch_trsm_w(int trans, const void *W, int w_f32, int64_t ldw, int64_t n, const double *sb, double *V,
+                  int64_t ldv, double *X, int64_t ldx, int64_t k, int f32, hipStream_t st)
+{
+    const int64_t SB = trsv_sb_rows();
+    const int64_t nsb = cdiv(n, SB), blk = SB * SB;
+    const double *Uinv = sb, *UinvT = sb + nsb * blk;
+    const size_t esz = w_f32 ? sizeof(float) : sizeof(double);
+    const char *Wb = (const char *)W;
+    if (!trans) {
+        // c = D^-1 V, then from the bottom: X_{<S} -= W_{<S,S} X_S
+        int rc = sb_diag_products(Uinv, V, ldv, X, ldx, n, k, f32, st);
+        if (rc) return rc;
+        for (int64_t S = nsb - 1; S >= 1; --S) {
+            const int64_t s0 = S * SB, r = std::min<int64_t>(SB, n - s0);
+            GemmDesc u{};
+            u.m = s0; u.n = k; u.k = r;
+            u.A = Wb + esz * (size_t)s0; u.lda = ldw; u.a_layout = 1; u.a_f32 = w_f32;   // A(i, t) = W[i, s0 + t]
+            u.B = X + s0; u.ldb = ldx; u.b_layout = 0;
+            u.C = X; u.ldc = ldx; u.c_layout = 0;
+            u.alpha = -1.0; u.beta = 1.0;
+            u.f32 = f32;
+            if ((rc = launch_gemm(u, st))) return rc;
+        }
+        return 0;
+    }
+    // y = (I + W)^-T V in V, from the top: V_{>S} -= W_{S,>S}^T V_S; then X = D^-T y
+    for (int64_t S = 0; S + 1 < nsb; ++S) {
+        const int64_t s0 = S * SB, s1 = s0 + SB;
+        GemmDesc u{};
+        u.m = n - s1; u.n = k; u.k = SB;
+        u.A = Wb + esz * (size_t)(s0 * ldw + s1); u.lda = ldw; u.a_layout = 0; u.a_f32 = w_f32;  // A(i, t) = W[s0 + t, s1 + i]
+        u.B = V + s0; u.ldb = ldv; u.b_layout = 0;
+        u.C = V + s1; u.ldc = ldv; u.c_layout = 0;
+        u.alpha = -1.0; u.beta = 1.0;
+        u.f32 = f32;
+        const int rc = launch_gemm(u, st);
+        if (rc) return rc;
+    }
+    return sb_diag_products(UinvT, V, ldv, X, ldx, n, k, f32, st);
+}
+
 // ------------------------------------------------------------ refinement
 namespace {
 

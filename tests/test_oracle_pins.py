@@ -299,3 +299,25 @@ def test_splitmix64_published_vector():
     expected = [2.0 * ((x >> 11) * 2.0 ** -53) - 1.0 for x in expected_u64]
     assert np.array_equal(v, np.array(expected))
     assert i.dtype == np.uint64
+
+
+def test_blocked_device_generator_known_spectrum(orc):
+    """The row-blocked generator used for n beyond single-tensor kernels:
+    the pencil's eigenvalues (oracle, FP64) are the drawn lam, A and B are
+    exactly symmetric and B = U^T U is positive definite (run on the CPU
+    device with blocks much smaller than n)."""
+    torch = pytest.importorskip("torch")
+    n = 200
+    d = gen.known_spectrum_device_blocked(n, "clustered", stream=(99,), device="cpu", nb=48, rank=12)
+    A, B = d["A"].numpy(), d["B"].numpy()
+    assert np.array_equal(A, A.T) and np.array_equal(B, B.T)
+    lam, _ = orc.gsyeig(A, B, n)
+    assert np.max(np.abs(lam - np.sort(d["lam"]))) <= 1e-12 * np.abs(d["lam"]).max()
+
+
+def test_fem_device_pencil_equals_host():
+    torch = pytest.importorskip("torch")
+    for n in (1, 2, 47, 130):
+        K, M = gen.fem_pencil_device(n, "cpu", nb=16)
+        K0, M0 = gen.fem_pencil(n)
+        assert np.array_equal(K.numpy(), K0) and np.array_equal(M.numpy(), M0)
