@@ -319,7 +319,7 @@ def bench_block(args, cfg):
             f"{inf.t_rr_ms:.0f} in {inf.rr_count}], KI5 {inf.t_ki5_ms:.0f}, BT1 {inf.t_bt1_ms:.0f}, refine "
             f"{inf.t_refine_ms:.0f}, check {inf.t_check_ms:.0f}) ops={inf.steps} restarts={inf.restarts} "
             f"basis={inf.basis} kept={inf.kept} eta={inf.eta_max:.2e} eta1={inf.eta_phase1:.2e} "
-            f"rounds={inf.refine_iters}")
+            f"rounds={inf.refine_iters} cluster_fallbacks={inf.cluster_fallbacks} (reason {inf.fallback_reason})")
 
     for w in range(args.warmup):
         dt, inf = run(A, B, B0, opts())

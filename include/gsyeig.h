@@ -141,6 +141,10 @@ typedef struct {
     int64_t kept;          /* Ritz vectors kept at a restart                    */
     double t_rr_ms;        /* projected eigen-solves of the checks (in t_ki_ms) */
     int64_t rr_count;      /* number of those                                   */
+    int64_t cluster_fallbacks; /* eigenvector sets that needed the sequential  */
+                           /*   Gram-Schmidt-in-clusters path (diagnostic)      */
+    int64_t fallback_reason; /* last one: 1 = two vectors overlapped > 0.5,   */
+                           /*   2 = their Gram matrix was not positive definite */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */

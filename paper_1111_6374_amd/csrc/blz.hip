@@ -472,7 +472,7 @@ int blz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const BlkOp &
                                w.Hw);
             TRY(ok());
             HIP_TRY(hipEventRecord(ctx->ev[2], st));
-            TRY(syev_small(ctx, N, w.Hw, d.nq, o->which, w.w, w.S, w.sy, st));
+            TRY((ctx->syev_site = 1, syev_small(ctx, N, w.Hw, d.nq, o->which, w.w, w.S, w.sy, st)));
             HIP_TRY(hipEventRecord(ctx->ev[3], st));
             hipLaunchKernelGGL(k_blk_resid, dim3(1), dim3(256), 0, st, Racc, (int)b, w.S, N, wanted0, s, w.w,
                                d.nq, tol, nconv_d, ratio_d);
@@ -514,7 +514,7 @@ int blz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const BlkOp &
         if (N < d.nq) return GSYEIG_ENOCONV;
         hipLaunchKernelGGL(k_mirror_upper, dim3((unsigned)cdiv(N * N, 256)), dim3(256), 0, st, w.H, ldh, N, w.Hw);
         TRY(ok());
-        TRY(syev_small(ctx, N, w.Hw, d.nq, o->which, w.w, w.S, w.sy, st));
+        TRY((ctx->syev_site = 1, syev_small(ctx, N, w.Hw, d.nq, o->which, w.w, w.S, w.sy, st)));
     }
     HIP_TRY(hipEventRecord(ctx->ev[7], st));
     // Ritz vectors Y = V S for the nvec pairs nearest the wanted end

@@ -271,7 +271,7 @@ static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double
 // on inverse-iteration eigenvectors of T_m, whose mutual overlaps are tiny
 // except inside clusters of close eigenvalues; there any orthonormal basis
 // of the computed vectors is as good.  *info_d != 0 if G was not positive
-// definite or if two columns overlapped by more than 1e-4 (the caller then
+// definite or if two columns overlapped by more than 0.5 (the caller then
 // falls back to sequential Gram-Schmidt with extra inverse-iteration solves).
 int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d)
 {
@@ -293,11 +293,13 @@ int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64
         g.alpha = 1.0; g.beta = 0.0;
         g.splitk = (int)sk; g.part = part;
         TRY(launch_gemm(g, ctx->stream));
-        // overlaps beyond 1e-4 mean near-equal Ritz values whose independent
-        // inverse-iteration vectors may be near-parallel: those need the
-        // sequential treatment (extra solves inside the cluster).  Smaller
-        // overlaps (about u ||T|| / gap) are removed by the two passes.
-        if (pass == 0) TRY(launch_flag_offdiag(G, nw, 1e-4, info_d, ctx->stream));
+        // Inverse-iteration vectors (random start per index) overlap by about
+        // u ||T|| / gap; inside a tight cluster they are independent mixtures
+        // of the cluster's eigenvectors, of which any orthonormal basis is as
+        // accurate, and the two passes make them orthonormal.  Only vectors
+        // that came out nearly parallel (overlap beyond 0.5) need the
+        // sequential treatment (extra solves inside the cluster).
+        if (pass == 0) TRY(launch_flag_offdiag(G, nw, 0.5, info_d, ctx->stream));
         TRY(potrf_core(ctx, nw, G, nw, Dv, info2));
         TRY(launch_accum_info(info2, info_d, ctx->stream));
         // Ri = R^-1 (column-major; R is G's upper triangle, row-major)
@@ -483,8 +485,11 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     TRY(orthonormalise_cols(ctx, m, nvec, S, m, oinfo_d));
     HIP_TRY(hipMemcpyAsync(nconv_h, oinfo_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (*nconv_h != 0)  // Gram matrix not positive definite: sequential Gram-Schmidt in clusters
+    if (*nconv_h != 0) {  // near-parallel vectors or Gram not positive definite: sequential Gram-Schmidt in clusters
+        ctx->n_fallback += 1;
+        ctx->fallback_why = 1;
         TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
+    }
     GemmDesc d{};
     d.m = n; d.n = nvec; d.k = m;
     d.A = V; d.lda = ldv; d.a_layout = 0;
@@ -1138,6 +1143,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (ldb < n) return -7;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
+    if (!o.invert) ctx->n_fallback = ctx->fallback_why = 0;
     if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block < 1 || (o.invert != 0 && o.invert != 1) ||
         (o.which != 0 && o.which != 1))
         return -8;
@@ -1145,8 +1151,23 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (!Lambda) return -9;
     if (!X) return -10;
     if (ldx < n) return -11;
-    if (o.invert) return solve_inverted(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
-    if (o.prec == GSYEIG_MIXED) return solve_mixed(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
+    if (o.invert) {
+        ctx->n_fallback = 0;
+        const int rc = solve_inverted(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
+        if (info) {
+            info->cluster_fallbacks = ctx->n_fallback;
+            info->fallback_reason = ctx->fallback_why;
+        }
+        return rc;
+    }
+    if (o.prec == GSYEIG_MIXED) {
+        const int rc = solve_mixed(ctx, n, s, A, lda, B, ldb, o, Lambda, X, ldx, info);
+        if (info) {
+            info->cluster_fallbacks = ctx->n_fallback;
+            info->fallback_reason = ctx->fallback_why;
+        }
+        return rc;
+    }
 
     gsyeig_info inf;
     memset(&inf, 0, sizeof(inf));
@@ -1212,6 +1233,8 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.kept = br.keep;
     inf.t_rr_ms = br.t_rr_ms;
     inf.rr_count = br.rr_count;
+    inf.cluster_fallbacks = ctx->n_fallback;
+    inf.fallback_reason = ctx->fallback_why;
     if (info) *info = inf;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
 }

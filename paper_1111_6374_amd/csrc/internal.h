@@ -84,6 +84,10 @@ struct gsyeig_ctx {
     int npev;             // events recorded since the last harvest
     int64_t prof_samples;
     double prof_ms[3];
+    int64_t n_fallback;   // clustered Gram-Schmidt fallbacks of the eigenvector orthonormalisation
+    int64_t fallback_why; // last reason: 1 = overlap above the threshold, 2 = Gram not positive definite,
+                          // plus 10 x the calling site (syev_site)
+    int syev_site;        // caller of the small eigensolver: 1 block Lanczos, 2 SVQB, 3 Rayleigh-Ritz
     gsyeig_ctx *workers[GSYEIG_MAX_STREAMS];  // batched-solve worker contexts
     hipStream_t wstreams[GSYEIG_MAX_STREAMS];
     int nworkers;
@@ -243,11 +247,14 @@ size_t syev_small_scratch(int64_t N, int64_t nwant);
 // ctx != NULL: eigenvectors by independent inverse iteration made orthonormal
 // by Cholesky QR twice, the clustered Gram-Schmidt path only when that finds
 // near-parallel vectors (synchronises); ctx == NULL: always clustered.
+// floor_rel > 0 (which = 0): eigenvectors of eigenvalues with w + floor_shift
+// <= floor_rel * (max + floor_shift) are not wanted (computed, but not
+// orthonormalised or checked).
 int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
-               double *scratch, hipStream_t st);
+               double *scratch, hipStream_t st, double floor_rel = 0.0, double floor_shift = 0.0);
 // Cholesky QR twice on the nw columns of S (m x nw, column-major); *info_d
 // != 0 when the Gram matrix was not positive definite or two columns
-// overlapped by more than 1e-4 (two device ints)
+// overlapped by more than 0.5 (two device ints)
 int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d);
 int64_t syev_small_max();
 

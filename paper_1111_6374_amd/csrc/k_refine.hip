@@ -321,6 +321,20 @@ __global__ void k_symmetrise(double *H, int64_t ld, int64_t N)
     H[i * ld + j] = v;
 }
 
+// H(i, i) += a  (N x N, ld)
+__global__ void k_diag_shift(double *H, int64_t ld, int64_t N, double a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) H[i * ld + i] += a;
+}
+
+// v[i] += a
+__global__ void k_vec_shift(double *v, int64_t n, double a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] += a;
+}
+
 // Gram matrix G (r x r): dsc_i = G_ii^-1/2 (0 for a non-positive diagonal)
 __global__ void k_gram_diag(const double *G, int64_t r, double *dsc)
 {
@@ -710,8 +724,24 @@ static int sytrd_launch(int64_t N, double *H, double *d, double *e, double *tau,
 // Eigenpairs of a symmetric N x N matrix H (column-major, ld N; destroyed):
 // the nwant smallest (which = 0) or largest (which = 1), ascending, into
 // w[0..nwant) (w[nwant] = the opposite extreme) and Q (N x nwant, ld N).
+// *k0 = number of i with w[i] + shift <= floor_rel * (w[n - 1] + shift) (w ascending)
+__global__ void k_count_floor(const double *w, int64_t n, double floor_rel, double shift, int *k0)
+{
+    __shared__ int s_c[256];
+    const double thr = floor_rel * (w[n - 1] + shift);
+    int c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) c += (w[i] + shift <= thr) ? 1 : 0;
+    s_c[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s_c[threadIdx.x] += s_c[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *k0 = s_c[0];
+}
+
 int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
-               double *scratch, hipStream_t st)
+               double *scratch, hipStream_t st, double floor_rel, double floor_shift)
 {
     if (N < 1 || N > SYTRD_MAX || nwant < 1 || nwant > N) return GSYEIG_EHIP;
     double *d = scratch, *e = d + N, *tau = e + N, *tri = tau + N + 8;
@@ -727,10 +757,24 @@ int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, 
         // near-parallel (tight clusters), which takes the clustered path
         int *info_d = (int *)ctx->dscal + 26;
         int *h = (int *)ctx->host_pinned + 26;
-        RTRY_HIP(orthonormalise_cols(ctx, N, nwant, Q, N, info_d));
-        if (hipMemcpyAsync(h, info_d, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GSYEIG_EHIP;
+        // eigenvectors at or below the floor are not wanted by the caller:
+        // neither made orthonormal nor checked
+        int64_t k0 = 0;
+        if (floor_rel > 0.0 && which == 0) {
+            int *k0_d = (int *)ctx->dscal + 28;
+            hipLaunchKernelGGL(k_count_floor, dim3(1), dim3(256), 0, st, w, nwant, floor_rel, floor_shift, k0_d);
+            if (ok()) return GSYEIG_EHIP;
+            if (hipMemcpyAsync(h + 2, k0_d, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GSYEIG_EHIP;
+            if (hipStreamSynchronize(st) != hipSuccess) return GSYEIG_EHIP;
+            k0 = std::min<int64_t>(h[2], nwant);
+        }
+        if (k0 < nwant) RTRY_HIP(orthonormalise_cols(ctx, N, nwant - k0, Q + k0 * N, N, info_d));
+        else if (hipMemsetAsync(info_d, 0, 2 * sizeof(int), st) != hipSuccess) return GSYEIG_EHIP;
+        if (hipMemcpyAsync(h, info_d, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GSYEIG_EHIP;
         if (hipStreamSynchronize(st) != hipSuccess) return GSYEIG_EHIP;
         if (*h != 0) {
+            ctx->n_fallback += 1;
+            ctx->fallback_why = ((h[1] != 0) ? 2 : 1) + 10 * ctx->syev_site;
             rc = launch_tri_vectors(d, e, N, nwant, w, Q, N, tri, 1, nullptr, st);
             if (rc) return rc;
         }
@@ -978,7 +1022,16 @@ int svqb(Ctx &c, int z, int64_t c0, int64_t r, double drop, int64_t *kept)
     RTRY(ok());
     hipLaunchKernelGGL(k_gram_apply, dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, st, b.C1, r, b.dsc);
     RTRY(ok());
-    RTRY(syev_small(c.ctx, r, b.C1, r, 0, b.theta, b.Qc, b.sy, st));
+    // decompose G - I (same eigenvectors; the subtraction is exact): for a
+    // nearly B-orthonormal block every eigenvalue of G is 1 to working
+    // precision, a numerically multiple cluster, while those of G - I are
+    // spread relative to its own norm
+    hipLaunchKernelGGL(k_diag_shift, dim3((unsigned)cdiv(r, 256)), dim3(256), 0, st, b.C1, r, r, -1.0);
+    RTRY(ok());
+    c.ctx->syev_site = 2;
+    RTRY(syev_small(c.ctx, r, b.C1, r, 0, b.theta, b.Qc, b.sy, st, drop, 1.0));
+    hipLaunchKernelGGL(k_vec_shift, dim3((unsigned)cdiv(r, 256)), dim3(256), 0, st, b.theta, r, 1.0);
+    RTRY(ok());
     std::vector<double> sig((size_t)r);
     HIP_TRY(hipMemcpyAsync(sig.data(), b.theta, sizeof(double) * (size_t)r, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1010,6 +1063,7 @@ int rayleigh_ritz(Ctx &c, int z, int64_t N, int64_t nk, int which, int *znew)
     RTRY(gemm_tn(b.Z[z], b.ldr, b.AZ[z], b.ldr, c.n, N, N, b.H, N, 1.0, 0.0, b.part, b.part_elems, st));
     hipLaunchKernelGGL(k_symmetrise, dim3((unsigned)cdiv(N * N, 256)), dim3(256), 0, st, b.H, N, N);
     RTRY(ok());
+    c.ctx->syev_site = 3;
     RTRY(syev_small(c.ctx, N, b.H, nk, which, b.theta, b.Qc, b.sy, st));
     const int oz = 1 - z;
     RTRY(gemm_nn(b.Z[z], b.ldr, b.Qc, N, c.n, N, nk, b.Z[oz], b.ldr, 1.0, 0.0, st));

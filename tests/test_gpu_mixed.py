@@ -409,3 +409,24 @@ def test_inverse_pencil_rejects_indefinite_a(gs, ctx, torch):
     Xd = torch.zeros(s, n, dtype=torch.float64, device="cuda")
     rc, _ = gs.gsyeig_solve(ctx, n, s, dev(torch, d["A"]), n, dev(torch, d["B"]), n, o, Lam, Xd, n)
     assert 1 <= rc <= n
+
+
+@pytest.mark.parametrize("N,nwant,width", [(600, 600, 1e-7), (1000, 1000, 1e-9), (800, 300, 1e-12)])
+def test_syev_small_gram_like_cluster(gs, ctx, torch, orc, N, nwant, width):
+    """Gram-like matrices (all eigenvalues within `width` of 1, as the
+    refinement's B-Gram matrices of nearly B-orthonormal blocks): the
+    eigenvectors must come out orthonormal with small residuals whichever
+    path (Cholesky QR or the clustered fallback) produced them."""
+    g = gen.rng(gen.BASE_SEED, 41, N)
+    Q, _ = np.linalg.qr(g.standard_normal((N, N)))
+    w_true = 1.0 + width * (2.0 * g.random(N) - 1.0)
+    H = (Q * w_true[None, :]) @ Q.T
+    H = 0.5 * (H + H.T)
+    say("syev_small gram-like", N, nwant, width)
+    wd = torch.zeros(nwant, dtype=torch.float64, device="cuda")
+    Qd = torch.zeros(nwant, N, dtype=torch.float64, device="cuda")
+    assert gs.gsyeig_syev_small(ctx, N, dev(torch, H), N, nwant, 0, wd, Qd, N) == 0
+    w, V = host(wd), host(Qd).T
+    assert np.max(np.abs(w - np.sort(w_true)[:nwant])) <= 50 * N * U64
+    assert np.linalg.norm(V.T @ V - np.eye(nwant)) <= 100 * N * U64
+    assert np.linalg.norm(H @ V - V * w[None, :]) <= 100 * N * U64
