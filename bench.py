@@ -27,7 +27,7 @@ CONFIGS = {
     3: dict(n=65536, s=800, law="spaced", prec="mixed", block=32,
             label="known-spectrum pencil n=65536 s=800 + 1-D FEM pencil (inverse pencil), block Lanczos, "
                   "mixed FP32 block products + FP64 refinement"),
-    4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n), FP64"),
+    4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n)"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -91,7 +91,11 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (exploration; the config label then says so)")
     ap.add_argument("--s", type=int, default=0, help="override s")
     ap.add_argument("--no-fp64-compare", action="store_true", help="--config 2: skip the FP64 solve")
-    ap.add_argument("--block", type=int, default=0, help="--config 3: block size (default 32)")
+    ap.add_argument("--block", type=int, default=0,
+                    help="Lanczos block size (--config 3: default 32; --config 2/4: default 1, single-vector)")
+    ap.add_argument("--prec", type=int, default=-1,
+                    help="--config 4: 0 = FP64, 1 = mixed (default: mixed, the configuration's precision)")
+    ap.add_argument("--no-loop", action="store_true", help="--config 4: skip the loop of single FP64 solves")
     ap.add_argument("--basis", type=int, default=0, help="--config 3: basis size before a restart (0 = auto)")
     ap.add_argument("--acc32", type=int, default=0, help="--config 3: 1 = FP32 accumulation in block products")
     ap.add_argument("--no-fem", action="store_true", help="--config 3: skip the FEM pencil")
@@ -456,6 +460,8 @@ def bench_mixed(args, cfg):
         o = gs.gsyeig_opts_default()
         o.prec = prec
         o.profile_every = args.profile_every
+        if args.block > 1:
+            o.block = args.block
         B.copy_(B0)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -568,10 +574,16 @@ def bench_batched(args, cfg):
             b.copy_(b0)
         torch.cuda.synchronize()
 
+    prec = gs.GSYEIG_MIXED if args.prec != 0 else gs.GSYEIG_FP64
+    o = gs.gsyeig_opts_default()
+    o.prec = prec
+    if args.block > 1:
+        o.block = args.block
+
     def batched():
         restore()
         t = time.perf_counter()
-        rc, status, infos = gs.gsyeig_solve_batched(solver.ctx, sizes, ss, A, sizes, B, sizes, None, Lam, X,
+        rc, status, infos = gs.gsyeig_solve_batched(solver.ctx, sizes, ss, A, sizes, B, sizes, o, Lam, X,
                                                     sizes, nstreams=args.streams)
         torch.cuda.synchronize()
         if rc:
@@ -586,27 +598,30 @@ def bench_batched(args, cfg):
         dt, infos = batched()
         times.append(dt)
         log(f"step {k}: batched {dt:.2f} s")
-    # reference: the same instances as a loop of single-instance FP64 solves
-    restore()
-    t = time.perf_counter()
-    for i, n in enumerate(sizes):
-        rc, _ = gs.gsyeig_solve(solver.ctx, n, ss[i], A[i], n, B[i], n, None, Lam[i], X[i], n)
-        if rc:
-            raise gs.GsyeigError("gsyeig_solve", rc)
-    torch.cuda.synchronize()
-    t_loop = time.perf_counter() - t
-    log(f"loop of single solves: {t_loop:.2f} s")
     e_lam = max(float(np.max(np.abs(L.cpu().numpy() - lt))) for L, lt in zip(Lam, lam_true))
     eta = max(i.eta_max for i in infos)
+    # reference: the same instances as a loop of single-instance plain FP64 solves
+    t_loop = None
+    if not args.no_loop:
+        restore()
+        t = time.perf_counter()
+        for i, n in enumerate(sizes):
+            rc, _ = gs.gsyeig_solve(solver.ctx, n, ss[i], A[i], n, B[i], n, None, Lam[i], X[i], n)
+            if rc:
+                raise gs.GsyeigError("gsyeig_solve", rc)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t
+        log(f"loop of single FP64 solves: {t_loop:.2f} s")
     value = sum(times) / len(times)
     out = {
         "metric": "time-to-s-eigenpairs",
         "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32+f64" if prec == gs.GSYEIG_MIXED else "f64", "data": "synthetic",
         "config": {"workload": cfg["label"], "instances": len(sizes), "sum_n": sum(sizes),
-                   "streams": args.streams, "prec": "fp64", "parallelism": "single-gpu"},
-        "loop_of_single_solves_s": t_loop, "batched_speedup": t_loop / value,
+                   "streams": args.streams, "prec": "mixed" if prec == gs.GSYEIG_MIXED else "fp64",
+                   "block": max(1, args.block), "parallelism": "single-gpu"},
+        "loop_of_single_fp64_solves_s": t_loop, "batched_speedup": (t_loop / value) if t_loop else None,
         "lanczos_steps_total": int(sum(i.steps for i in infos)),
         "parity": {"e_lambda_vs_known": e_lam, "eta_max": eta, "pass": bool(e_lam <= 1e-10 and eta <= 1e-10)},
     }

@@ -28,7 +28,7 @@ EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
-    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_solve_batched",
+    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_fused_symv", "gsyeig_solve_batched",
     "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
 )
 
@@ -94,6 +94,7 @@ def lib():
             "gsyeig_create": ([ctypes.POINTER(P), P], I),
             "gsyeig_destroy": ([P], I),
             "gsyeig_set_trsv_block": ([P, I64], I),
+            "gsyeig_set_fused_symv": ([P, I], I),
             "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
             "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
             "gsyeig_trsv_lp": ([P, I64, P, I64, I, P, P], I),
@@ -161,6 +162,10 @@ def gsyeig_destroy(ctx) -> int:
 
 def gsyeig_set_trsv_block(ctx, rows) -> int:
     return lib().gsyeig_set_trsv_block(ctx, rows)
+
+
+def gsyeig_set_fused_symv(ctx, on) -> int:
+    return lib().gsyeig_set_fused_symv(ctx, on)
 
 
 def gsyeig_workspace_size(n, s, opts=None):

@@ -242,6 +242,25 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
+    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse && fused_symv_fits(n)) {
+        // KI1 with KI2 fused (one cooperative launch), then the fixed-order
+        // reduction of the tile partials
+        const int2 *items;
+        int ntiles;
+        double *Pr, *Pc;
+        TRY(symv_fused_prepare(ctx, n, &items, &ntiles, &Pr, &Pc));
+        TRY(launch_trsv_w_n_symv((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], w,
+                                 tmp, ctx->ctl_n, op.A, op.lda, items, ntiles, Pr, Pc, ctx->stream));
+        if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
+        TRY(launch_symv_reduce_tiles(Pr, Pc, n, z, ctx->stream));
+        if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
+        TRY(solve_t(ctx, n, op.U, op.ldu, op.Dinv, z, z));
+        if (sample) {
+            HIP_TRY(hipEventRecord(e[3], ctx->stream));
+            ctx->npev += 4;
+        }
+        return 0;
+    }
     if (op.f32)
         TRY(launch_trsv_w_n_f32(op.W32, op.ldw32, n, op.sb, w, tmp, ctx->ctl_n, ctx->stream));
     else
@@ -842,6 +861,7 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
     gsyeig_ctx *ctx = new (std::nothrow) gsyeig_ctx;
     if (!ctx) return GSYEIG_ENOMEM;
     memset(ctx, 0, sizeof(*ctx));
+    ctx->symv_fuse = 0;
     ctx->stream = (hipStream_t)hip_stream;
     ctx->symv_map_n = -1;
     ctx->trsv_block = 512;
@@ -888,6 +908,14 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
     if (!ctx) return -1;
     if (rows != 64 && rows != trsv_sb_rows()) return -2;
     ctx->trsv_block = rows;
+    return 0;
+}
+
+int gsyeig_set_fused_symv(gsyeig_ctx *ctx, int on)
+{
+    if (!ctx) return -1;
+    if (on != 0 && on != 1) return -2;
+    ctx->symv_fuse = on;
     return 0;
 }
 

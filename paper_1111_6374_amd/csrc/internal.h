@@ -28,7 +28,7 @@ struct PCtl {
     unsigned ticket;
     unsigned done;
     unsigned err;
-    unsigned pad;
+    unsigned pad;   // work-queue counter of a fused second phase (reset with the others)
 };
 #define PCTL_STAGE_OFFSET 256
 #define STAGE_SENTINEL 0xFFFFFFFFFFFFFFFFull
@@ -63,6 +63,7 @@ enum WsSlot {
     WS_INV,        // mu and vectors of the inverse-pencil solve
     WS_W,          // W = blockdiag(U_SS)^-1 U_offdiag for the super-block solves (FP64 or FP32)
     WS_BLZ,        // block Lanczos: projected matrix, Ritz coefficients, blocks, kept Ritz vectors
+    WS_SYMVFUSE,   // tile queue of the fused KI1 + KI2 sweep
     WS_COUNT
 };
 
@@ -77,6 +78,8 @@ struct gsyeig_ctx {
     int64_t trsv_block; // 64: chained 64-row solves; 512: super-block solves
     int64_t symv_map_n; // n for which WS_SYMVMAP is valid
     int64_t symv_items;
+    int64_t symv_fuse_n;  // n for which WS_SYMVFUSE is valid
+    int symv_fuse;        // 1: fuse KI2 into KI1 where the grid can be resident (FP64 path)
     void *host_pinned;  // small pinned host staging area
     void *dscal;        // small device scratch (info codes, counters, check results)
     hipEvent_t ev[8];
@@ -146,6 +149,15 @@ int launch_trsv_w_t(const double *W, int64_t ldw, int64_t n, const double *sbw, 
                     PCtl *ctl, hipStream_t st);
 int launch_trsv_w_n_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
                         PCtl *ctl, hipStream_t st);
+// KI1 with KI2 fused (FP64): x = U^-1 b and the per-tile partials of A x
+// (then launch_symv_reduce_tiles); GSYEIG_EHIP if the grid cannot be resident
+int fused_symv_fits(int64_t n);
+int launch_trsv_w_n_symv(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                         PCtl *ctl, const double *A, int64_t lda, const int2 *items, int ntiles, double *Pr,
+                         double *Pc, hipStream_t st);
+// the tile work list (release order) and partial buffers of the fused form
+int symv_fused_prepare(gsyeig_ctx *ctx, int64_t n, const int2 **items, int *ntiles, double **Pr, double **Pc);
+int launch_symv_reduce_tiles(const double *Pr, const double *Pc, int64_t n, double *y, hipStream_t st);
 int launch_trsv_w_t_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
                         PCtl *ctl, hipStream_t st);
 int launch_potrf_diag_f32(float *B, int64_t ldb, int64_t n, int64_t kb, double *Dinv, int *info,

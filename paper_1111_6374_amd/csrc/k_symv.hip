@@ -196,11 +196,11 @@ __global__ __launch_bounds__(256) void k_symv_tiles_f32(const float *__restrict_
 // reading 2 KB of contiguous partials per step; a fixed-order LDS fold ends it.
 __global__ __launch_bounds__(256) void k_symv_reduce(const double *__restrict__ Pr,
                                                      const double *__restrict__ Pc, int nblk,
-                                                     int maxch, int64_t n, double *__restrict__ y)
+                                                     int maxch, int64_t n, double *__restrict__ y, int ch)
 {
     __shared__ double sred[4][NB];
     const int K = blockIdx.x, t = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int nch = (nblk - K + SYMV_CH - 1) / SYMV_CH;
+    const int nch = (nblk - K + ch - 1) / ch;
     double s = 0.0;
     for (int ch = q; ch < nch; ch += 4) s += Pr[((int64_t)K * maxch + ch) * NB + t];
     const double *pc = Pc + (int64_t)K * nblk * NB + t;
@@ -253,7 +253,42 @@ static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, co
                            lda, n, nblk, maxch, x, (const int2 *)ctx->ws[WS_SYMVMAP], (double *)pr, (double *)pc);
     if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
-                       (const double *)pc, nblk, maxch, n, y);
+                       (const double *)pc, nblk, maxch, n, y, SYMV_CH);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+// Work list of the fused KI1 + KI2 sweep: single 64x64 tiles (I, J >= I) of
+// the upper triangle, block rows from the bottom (the order of the sweep);
+// per-tile row partials (maxch = nblk).
+int symv_fused_prepare(gsyeig_ctx *ctx, int64_t n, const int2 **items, int *ntiles, double **Pr, double **Pc)
+{
+    const int nblk = (int)cdiv(n, NB);
+    int rc;
+    void *p;
+    const size_t cnt = (size_t)nblk * (nblk + 1) / 2;
+    if (ctx->symv_fuse_n != n) {
+        std::vector<int2> it;
+        it.reserve(cnt);
+        for (int I = nblk - 1; I >= 0; --I)
+            for (int J = I; J < nblk; ++J) it.push_back(make_int2(I, J));
+        if ((rc = ws_get(ctx, WS_SYMVFUSE, it.size() * sizeof(int2), &p))) return rc;
+        HIP_TRY(hipMemcpyAsync(p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->symv_fuse_n = n;
+    }
+    *items = (const int2 *)ctx->ws[WS_SYMVFUSE];
+    *ntiles = (int)cnt;
+    if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * nblk * NB, &p))) return rc;
+    *Pr = (double *)p;
+    if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &p))) return rc;
+    *Pc = (double *)p;
+    return 0;
+}
+
+int launch_symv_reduce_tiles(const double *Pr, const double *Pc, int64_t n, double *y, hipStream_t st)
+{
+    const int nblk = (int)cdiv(n, NB);
+    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, st, Pr, Pc, nblk, nblk, n, y, 1);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 

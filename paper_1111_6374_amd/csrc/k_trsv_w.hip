@@ -31,10 +31,112 @@ namespace {
 using namespace chain;
 
 // ------------------------------------------------------------------ KI1
-template <typename T>
+// KI2 fused into the KI1 sweep (optional, SYMV = true): once a workgroup has
+// published its 64 values, its four 256-thread quarters take 64x64 tiles
+// (I, J >= I) of A's upper triangle from a queue ordered by block row from
+// the bottom (the order in which the sweep publishes x), wait (bounded) for
+// x_I and x_J on the staging vector, and apply each tile both ways --
+// y_I += A_IJ x_J, and y_J += A_IJ^T x_I for J > I -- into per-tile
+// partials that k_symv_reduce sums in a fixed order.  The SYMV stream
+// thereby runs in the bandwidth the latency-bound sweep leaves idle.  The
+// waits are safe only if every workgroup is resident: the fused form is
+// launched cooperatively.
+struct SymvFuse {
+    const void *A; int64_t lda;
+    const int2 *items;   // (I, J) tiles in queue order
+    int ntiles;
+    double *Pr, *Pc;     // row partials [I][J - I][64], column partials [J][I][64]
+};
+
+constexpr int FUSE_GRAB = 16;  // tiles per queue ticket: 4 per quarter
+
+template <typename TA>
+__device__ __forceinline__ void symv_one_tile(const SymvFuse &sf, int64_t n, int nblk, double *stage, PCtl *ctl,
+                                              double (*s_sp)[4][NB], int t)
+{
+    const TA *A = (const TA *)sf.A;
+    const int tid = threadIdx.x;
+    const int qd = tid >> 8, qt = tid & 255, ql = qt & 63, qw = qt >> 6;
+    const int c = 16 * qw + (ql & 15), rg = ql >> 4;
+    const bool have = t < sf.ntiles;
+    int I = 0, J = 0;
+    if (have) {
+        const int2 it = sf.items[t];
+        I = it.x;
+        J = it.y;
+    }
+    const int64_t r0 = (int64_t)I * NB, col = (int64_t)J * NB + c;
+    const bool colok = have && col < n;
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t row = r0 + rg + 4 * q;
+        a[q] = (colok && row < n) ? (double)A[row * sf.lda + col] : 0.0;
+    }
+    const double *pj = stage + (colok ? col : 0);
+    const unsigned long long vj = ld_bits(pj);
+    unsigned long long vi[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t row = r0 + rg + 4 * q;
+        vi[q] = ld_bits(stage + ((have && row < n) ? row : 0));
+    }
+    const double xj = colok ? settle(vj, pj, &ctl->err) : 0.0;
+    double acc[16], cs = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t row = r0 + rg + 4 * q;
+        const double xi = (have && row < n) ? settle(vi[q], stage + row, &ctl->err) : 0.0;
+        acc[q] = a[q] * xj;
+        cs = fma(a[q], xi, cs);
+    }
+    // column part (J > I): sum over the tile's 64 rows
+    cs += __shfl_xor(cs, 16);
+    cs += __shfl_xor(cs, 32);
+    if (have && J > I && rg == 0) sf.Pc[((int64_t)J * nblk + I) * NB + c] = cs;
+    // row part: sum over the 16 columns of this lane group, then over the 4 waves
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        double v = acc[q];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        acc[q] = v;
+    }
+    if ((ql & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s_sp[qd][qw][rg + 4 * q] = acc[q];
+    }
+    __syncthreads();
+    if (have && qt < NB)
+        sf.Pr[((int64_t)I * nblk + (J - I)) * NB + qt] =
+            (s_sp[qd][0][qt] + s_sp[qd][1][qt]) + (s_sp[qd][2][qt] + s_sp[qd][3][qt]);
+    __syncthreads();
+}
+
+// Tickets of FUSE_GRAB tiles; the next ticket is taken while the current
+// tiles are processed, so the queue's atomic is off the critical path.
+template <typename TA>
+__device__ __forceinline__ void symv_tiles_phase(const SymvFuse &sf, int64_t n, int nblk, double *stage, PCtl *ctl,
+                                                 double (*s_sp)[4][NB], int *s_tk)
+{
+    const int tid = threadIdx.x, qd = tid >> 8;
+    if (tid == 0) s_tk[0] = (int)atomicAdd(&ctl->pad, (unsigned)FUSE_GRAB);
+    __syncthreads();
+    int cur = s_tk[0];
+    for (int round = 0; cur < sf.ntiles; ++round) {
+        if (tid == 0) s_tk[(round + 1) & 1] = (int)atomicAdd(&ctl->pad, (unsigned)FUSE_GRAB);
+#pragma unroll 1
+        for (int u = 0; u < FUSE_GRAB / 4; ++u) symv_one_tile<TA>(sf, n, nblk, stage, ctl, s_sp, cur + 4 * qd + u);
+        cur = s_tk[(round + 1) & 1];  // written before the last __syncthreads of the tiles
+    }
+}
+
+template <typename T, typename TA, bool SYMV>
 __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int64_t ldw, int64_t n, int nblk,
                                                    const double *__restrict__ Uinv, const double *b, double *x,
-                                                   PCtl *ctl)
+                                                   PCtl *ctl, SymvFuse sf)
 {
     __shared__ int s_blk, s_last;
     double *stage = ctl_stage(ctl);
@@ -97,28 +199,31 @@ __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int6
         }
     }
 
-    // the link: rows of W_{S,S+1} (loaded before x_{S+1} can arrive), x_{S+1}
+    // the link: rows of W_{S,S+1} (loaded before x_{S+1} can arrive), x_{S+1}.
+    // Wave-uniform row pointers and 32-bit lane offsets keep the 32
+    // prefetched values and their addresses within the register budget.
     if (has_next) {
+        const int64_t k1 = s0 + SBR;                     // first column of S+1
+        const int lim = (int)(n - 1 - k1);               // last valid offset in S+1
+        const T *Wl[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wl[r] = W + (r0 + 4 * w + r) * ldw + k1;
+        const double *sl = stage + k1;
         double nr[TPS][4];
 #pragma unroll
         for (int c = 0; c < TPS; ++c) {
-            const int64_t k0 = s0 + SBR + (int64_t)c * NB + l;
-            const int64_t kc = k0 < n ? k0 : n - 1;
+            const int o = min(c * NB + l, lim);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) nr[c][r] = (double)W[(r0 + 4 * w + r) * ldw + kc];
+            for (int r = 0; r < 4; ++r) nr[c][r] = (double)Wl[r][o];
         }
         unsigned long long v[TPS];
 #pragma unroll
-        for (int c = 0; c < TPS; ++c) {
-            const int64_t k0 = s0 + SBR + (int64_t)c * NB + l;
-            v[c] = ld_bits(stage + (k0 < n ? k0 : n - 1));
-        }
+        for (int c = 0; c < TPS; ++c) v[c] = ld_bits(sl + min(c * NB + l, lim));
 #pragma unroll
         for (int c = 0; c < TPS; ++c) {
-            const int64_t k0 = s0 + SBR + (int64_t)c * NB + l;
-            const int64_t kk = k0 < n ? k0 : n - 1;
-            const double xv = settle(v[c], stage + kk, &ctl->err);
-            const double xn = (k0 < n) ? xv : 0.0;
+            const int o = c * NB + l;
+            const double xv = settle(v[c], sl + min(o, lim), &ctl->err);
+            const double xn = (o <= lim) ? xv : 0.0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) y[r] = fma(-nr[c][r], xn, y[r]);
         }
@@ -132,6 +237,11 @@ __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int6
             st_bits(stage + row, (unsigned long long)__double_as_longlong(xi));
             x[row] = xi;
         }
+    }
+    if constexpr (SYMV) {
+        __shared__ double s_sp[4][4][NB];
+        __shared__ int s_tk[2];
+        symv_tiles_phase<TA>(sf, n, nblk, stage, ctl, s_sp, s_tk);
     }
     retire(ctl, stage, n, nblk, &s_last);
 }
@@ -410,7 +520,8 @@ static int trsv_w_n_t(const T *W, int64_t ldw, int64_t n, const double *sbw, con
                       hipStream_t st)
 {
     const int nblk = (int)cdiv(n, NB);
-    hipLaunchKernelGGL(k_trsv_w_n<T>, dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw, b, x, ctl);
+    hipLaunchKernelGGL((k_trsv_w_n<T, T, false>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw, b, x, ctl,
+                       SymvFuse{});
     return ok();
 }
 
@@ -441,6 +552,40 @@ int launch_trsv_w_n_f32(const float *W, int64_t ldw, int64_t n, const double *sb
                         PCtl *ctl, hipStream_t st)
 {
     return trsv_w_n_t<float>(W, ldw, n, sbw, b, x, ctl, st);
+}
+
+// KI1 with KI2 fused (FP64 W and A): x = U^-1 b and the tile partials of
+// A x, cooperative launch.  Returns GSYEIG_EHIP when the grid cannot be
+// co-resident (the caller then runs the two kernels apart).
+int fused_symv_fits(int64_t n)
+{
+    static int max_blocks = -1;
+    if (max_blocks < 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_trsv_w_n<double, double, true>,
+                                                         1024, 0) != hipSuccess)
+            max_blocks = 0;
+        else
+            max_blocks = per_cu * cus;
+    }
+    return cdiv(n, NB) <= max_blocks;
+}
+
+int launch_trsv_w_n_symv(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                         PCtl *ctl, const double *A, int64_t lda, const int2 *items, int ntiles, double *Pr,
+                         double *Pc, hipStream_t st)
+{
+    if (!fused_symv_fits(n)) return GSYEIG_EHIP;
+    int nblk = (int)cdiv(n, NB);
+    SymvFuse sf{A, lda, items, ntiles, Pr, Pc};
+    void *args[] = {(void *)&W, (void *)&ldw, (void *)&n, (void *)&nblk, (void *)&sbw, (void *)&b, (void *)&x,
+                    (void *)&ctl, (void *)&sf};
+    if (hipLaunchCooperativeKernel((const void *)k_trsv_w_n<double, double, true>, dim3(nblk), dim3(1024), args, 0,
+                                   st) != hipSuccess)
+        return GSYEIG_EHIP;
+    return ok();
 }
 
 int launch_trsv_w_t_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
