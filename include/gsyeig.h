@@ -170,17 +170,20 @@ int gsyeig_destroy(gsyeig_ctx *ctx);
  * Host-only setting; takes effect at the next factorisation or solve. */
 int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
 
-/* KI2 fused into the KI1 sweep (FP64 operator with the 512-row super-block
- * solves): on = 1 lets the workgroups of the U^-1 sweep that have published
- * their rows apply the 64x64 tiles of A's upper triangle as the solved
- * values arrive (Section 2.3's KI1 and KI2 computed together), so the A
- * product streams in the bandwidth the latency-bound sweep leaves idle;
- * used only where every workgroup of the sweep can be resident at once
- * (n <= 64 x the resident 1024-thread workgroups, 16384 here), else the two
- * kernels run apart.  The result equals the unfused product up to the order
- * of the tile sums.  0 (default) = always apart: on MI355X at n = 16384 the
- * fused sweep saves only ~2 % (the tiles become available late in the
- * sweep and their traffic slows its chain).  Host-only setting. */
+/* KI2 fused into a triangular sweep (FP64 operator with the 512-row
+ * super-block solves; Section 2.3's KI1-KI3 computed with KI2 overlapped):
+ *   on = 1: into the U^-1 sweep -- workgroups that have published their rows
+ *           apply the 64x64 tiles of A's upper triangle as the solved values
+ *           arrive;
+ *   on = 2: into the U^-T sweep -- workgroups waiting for their turn apply
+ *           the tiles, block rows from the top (the order in which that sweep
+ *           needs A x), to the complete U^-1 result, and each sums its own
+ *           rows of A x before its link;
+ *   on = 0: the three kernels run apart.
+ * Fusion needs every workgroup of the sweep resident at once (cooperative
+ * launch; n <= 64 x the resident 1024-thread workgroups, 16384 here); where
+ * it is not, the kernels run apart.  The result equals the unfused operator
+ * up to the order of the partial sums.  Host-only setting. */
 int gsyeig_set_fused_symv(gsyeig_ctx *ctx, int on);
 
 /* Bytes of device workspace gsyeig_solve needs for (n, s, opts) (host-only

@@ -27,6 +27,8 @@ int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out)
         ctx->ws[slot] = nullptr;
         ctx->ws_bytes[slot] = 0;
         if (slot == WS_SYMVMAP) ctx->symv_map_n = -1;
+        if (slot == WS_SYMVFUSE) ctx->symv_fuse_n = -1;
+        if (slot == WS_FUSE3) ctx->fuse3_n = -1;
     }
     const size_t sz = (bytes + 4095) & ~(size_t)4095;
     void *p = nullptr;
@@ -80,7 +82,9 @@ static int ctl_check(gsyeig_ctx *ctx)
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (h[0] || h[1]) {
-        // a wait expired: restart both control blocks from a clean state
+        // a wait expired: restart both control blocks (and the fused sweep's
+        // sentinel partials) from a clean state
+        ctx->fuse3_n = -1;
         int rc;
         if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)))
             return rc;
@@ -242,7 +246,26 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
-    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse && fused_symv_fits(n)) {
+    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse == 2 && fused_ki3_fits(n)) {
+        // KI1, then KI2 and KI3 in one cooperative launch
+        const int2 *items;
+        int ntiles;
+        double *Pr, *Pc;
+        TRY(symv_fused3_prepare(ctx, n, &items, &ntiles, &Pr, &Pc));
+        TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
+        if (sample) {
+            HIP_TRY(hipEventRecord(e[1], ctx->stream));
+            HIP_TRY(hipEventRecord(e[2], ctx->stream));
+        }
+        TRY(launch_trsv_w_t_symv((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], op.A,
+                                 op.lda, tmp, z, ctx->ctl_t, items, ntiles, Pr, Pc, ctx->stream));
+        if (sample) {
+            HIP_TRY(hipEventRecord(e[3], ctx->stream));
+            ctx->npev += 4;
+        }
+        return 0;
+    }
+    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse == 1 && fused_symv_fits(n)) {
         // KI1 with KI2 fused (one cooperative launch), then the fixed-order
         // reduction of the tile partials
         const int2 *items;
@@ -914,7 +937,7 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
 int gsyeig_set_fused_symv(gsyeig_ctx *ctx, int on)
 {
     if (!ctx) return -1;
-    if (on != 0 && on != 1) return -2;
+    if (on < 0 || on > 2) return -2;
     ctx->symv_fuse = on;
     return 0;
 }

@@ -301,3 +301,33 @@ int launch_symv_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, con
 {
     return launch_symv_t<float>(ctx, n, A, lda, x, y);
 }
+
+// Queue and partials of the KI2 + KI3 fusion: tiles (I, J >= I), block rows
+// from the top; row and column partials (nblk x nblk x 64 each) filled with
+// the sentinel once (each launch leaves them so).
+int symv_fused3_prepare(gsyeig_ctx *ctx, int64_t n, const int2 **items, int *ntiles, double **Pr, double **Pc)
+{
+    const int nblk = (int)cdiv(n, NB);
+    const size_t cnt = (size_t)nblk * (nblk + 1) / 2;
+    const size_t itb = (cnt * sizeof(int2) + 255) & ~(size_t)255;
+    const size_t pb = sizeof(double) * (size_t)nblk * nblk * NB;
+    void *p;
+    int rc;
+    if ((rc = ws_get(ctx, WS_FUSE3, itb + 2 * pb, &p))) return rc;
+    char *base = (char *)p;
+    if (ctx->fuse3_n != n) {
+        std::vector<int2> it;
+        it.reserve(cnt);
+        for (int I = 0; I < nblk; ++I)
+            for (int J = I; J < nblk; ++J) it.push_back(make_int2(I, J));
+        HIP_TRY(hipMemcpyAsync(base, it.data(), cnt * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemsetAsync(base + itb, 0xFF, 2 * pb, ctx->stream));   // the sentinel: all ones
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->fuse3_n = n;
+    }
+    *items = (const int2 *)base;
+    *ntiles = (int)cnt;
+    *Pr = (double *)(base + itb);
+    *Pc = (double *)(base + itb + pb);
+    return 0;
+}

@@ -187,9 +187,11 @@ def test_apply_op_matches_oracle_and_known_c(gs, ctx, torch, orc, n, block):
 
 @pytest.mark.parametrize("n", [64, 1000, 4097, 16384])
 def test_fused_symv_equals_separate_kernels(gs, ctx, torch, orc, n):
-    """KI2 fused into the KI1 sweep (cooperative launch, per-tile partials)
-    against the two kernels run apart: the same operator up to the order of
-    the tile sums, and both against the oracle (small n)."""
+    """KI2 fused into the KI1 sweep (mode 1) or into the KI3 sweep (mode 2;
+    cooperative launches, per-tile partials) against the kernels run apart:
+    the same operator up to the order of the tile sums, and against the
+    oracle (small n).  Mode 2 runs again after mode 0 (its sentinel partials
+    must survive other launches)."""
     say("fused symv", n)
     assert gs.gsyeig_set_trsv_block(ctx, 512) == 0
     if n <= 4097:
@@ -201,17 +203,18 @@ def test_fused_symv_equals_separate_kernels(gs, ctx, torch, orc, n):
     w = gen.rng(116, n).standard_normal(n)
     wd = dev(torch, w)
     out = {}
-    for on in (1, 0):
+    for on in (1, 2, 0, 2):
         assert gs.gsyeig_set_fused_symv(ctx, on) == 0
         zd = torch.empty(n, dtype=torch.float64, device="cuda")
-        for _ in range(3):  # the counters and staging reset themselves between launches
+        for _ in range(3):  # the counters, staging and partials reset themselves between launches
             assert gs.gsyeig_apply_op(ctx, n, A, n, U, n, wd, zd) == 0
         out[on] = host(zd)
-    assert gs.gsyeig_set_fused_symv(ctx, 1) == 0
+    assert gs.gsyeig_set_fused_symv(ctx, 0) == 0
     scale = np.max(np.abs(out[0]))
-    assert np.max(np.abs(out[1] - out[0])) <= 1e-13 * scale * max(1.0, n / 1024)
-    if n <= 4097:
-        assert np.max(np.abs(out[1] - orc.apply_ki(d["A"], d["U"], w))) <= 1e-12 * np.max(np.abs(w))
+    for on in (1, 2):
+        assert np.max(np.abs(out[on] - out[0])) <= 1e-13 * scale * max(1.0, n / 1024)
+        if n <= 4097:
+            assert np.max(np.abs(out[on] - orc.apply_ki(d["A"], d["U"], w))) <= 1e-12 * np.max(np.abs(w))
 
 
 # --------------------------------------------------------------- KI4
