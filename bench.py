@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--profile-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=512, help="instances for --config 4")
-    ap.add_argument("--streams", type=int, default=8, help="worker streams for --config 4")
+    ap.add_argument("--streams", type=int, default=16, help="worker streams for --config 4")
     ap.add_argument("--n", type=int, default=0, help="override n (exploration; the config label then says so)")
     ap.add_argument("--s", type=int, default=0, help="override s")
     ap.add_argument("--no-fp64-compare", action="store_true", help="--config 2: skip the FP64 solve")
@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--prec", type=int, default=-1,
                     help="--config 4: 0 = FP64, 1 = mixed (default: mixed, the configuration's precision)")
     ap.add_argument("--no-loop", action="store_true", help="--config 4: skip the loop of single FP64 solves")
+    ap.add_argument("--refine-inner", type=int, default=0, help="MINRES steps per refinement round (0 = default)")
     ap.add_argument("--fuse", type=int, default=-1,
                     help="KI2 fusion (gsyeig_set_fused_symv): 0 apart, 1 into KI1, 2 into KI3 (default: library's)")
     ap.add_argument("--basis", type=int, default=0, help="--config 3: basis size before a restart (0 = auto)")
@@ -308,6 +309,8 @@ def bench_block(args, cfg):
         o.profile_every = args.profile_every
         if args.eta_tol > 0:
             o.eta_tol = args.eta_tol
+        if args.refine_inner > 0:
+            o.refine_inner = args.refine_inner
         for k, v in kw.items():
             setattr(o, k, v)
         return o
@@ -468,6 +471,8 @@ def bench_mixed(args, cfg):
         o.profile_every = args.profile_every
         if args.block > 1:
             o.block = args.block
+        if args.refine_inner > 0:
+            o.refine_inner = args.refine_inner
         B.copy_(B0)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -606,6 +611,13 @@ def bench_batched(args, cfg):
         log(f"step {k}: batched {dt:.2f} s")
     e_lam = max(float(np.max(np.abs(L.cpu().numpy() - lt))) for L, lt in zip(Lam, lam_true))
     eta = max(i.eta_max for i in infos)
+    # the batched driver in the other precision, same instances
+    t_other = None
+    if not args.no_loop:
+        o.prec = gs.GSYEIG_FP64 if prec == gs.GSYEIG_MIXED else gs.GSYEIG_MIXED
+        t_other, _ = batched()
+        log(f"batched, {'FP64' if o.prec == gs.GSYEIG_FP64 else 'mixed'}: {t_other:.2f} s")
+        o.prec = prec
     # reference: the same instances as a loop of single-instance plain FP64 solves
     t_loop = None
     if not args.no_loop:
@@ -628,6 +640,7 @@ def bench_batched(args, cfg):
                    "streams": args.streams, "prec": "mixed" if prec == gs.GSYEIG_MIXED else "fp64",
                    "block": max(1, args.block), "parallelism": "single-gpu"},
         "loop_of_single_fp64_solves_s": t_loop, "batched_speedup": (t_loop / value) if t_loop else None,
+        ("batched_fp64_s" if prec == gs.GSYEIG_MIXED else "batched_mixed_s"): t_other,
         "lanczos_steps_total": int(sum(i.steps for i in infos)),
         "parity": {"e_lambda_vs_known": e_lam, "eta_max": eta, "pass": bool(e_lam <= 1e-10 and eta <= 1e-10)},
     }
