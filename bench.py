@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--fem-only", action="store_true", help="--config 3: only the FEM pencil")
     ap.add_argument("--fem-prec", type=int, default=1, help="--config 3: FEM pencil precision (0 FP64, 1 mixed)")
     ap.add_argument("--eta-tol", type=float, default=0.0, help="refinement target (0 = library default)")
+    ap.add_argument("--reorth", type=int, default=-1,
+                    help="re-orthogonalisation: 0 twice, 1 second pass when needed, 2 partial (-1 = default)")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -155,6 +157,8 @@ def main():
             raise gs.GsyeigError("gsyeig_set_fused_symv", rc)
     opts = gs.gsyeig_opts_default()
     opts.profile_every = args.profile_every
+    if args.reorth >= 0:
+        opts.reorth = args.reorth
     Lam = torch.empty(s, dtype=torch.float64, device=dev)
     X = torch.empty(s, n, dtype=torch.float64, device=dev)
 
@@ -167,7 +171,7 @@ def main():
 
     for w in range(args.warmup):
         info = step()
-        log(f"warmup {w}: {info.t_total_ms:.1f} ms, steps={info.steps}")
+        log(f"warmup {w}: {info.t_total_ms:.1f} ms, steps={info.steps}, reorth_steps={info.reorth_steps}")
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
@@ -210,7 +214,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "fp64",
-                   "block": 1, "lanczos_steps": int(last.steps), "parallelism": "single-gpu"},
+                   "block": 1, "lanczos_steps": int(last.steps), "reorth": int(opts.reorth),
+                   "reorth_steps": int(last.reorth_steps), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
                      "traffic": measured_traffic("k_trsv_w", n, "fp64"),
@@ -471,6 +476,8 @@ def bench_mixed(args, cfg):
         o.profile_every = args.profile_every
         if args.block > 1:
             o.block = args.block
+        if args.reorth >= 0:
+            o.reorth = args.reorth
         if args.refine_inner > 0:
             o.refine_inner = args.refine_inner
         B.copy_(B0)
@@ -528,7 +535,8 @@ def bench_mixed(args, cfg):
         "warmup": args.warmup, "ms_per_step": 1e3 * value, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "mixed",
-                   "block": 1, "lanczos_steps": int(last.steps), "refine_rounds": int(last.refine_iters),
+                   "block": 1, "lanczos_steps": int(last.steps), "reorth_steps": int(last.reorth_steps),
+                   "refine_rounds": int(last.refine_iters),
                    "block_cols": int(last.block_cols), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
@@ -590,6 +598,8 @@ def bench_batched(args, cfg):
     o.prec = prec
     if args.block > 1:
         o.block = args.block
+    if args.reorth >= 0:
+        o.reorth = args.reorth
 
     def batched():
         restore()

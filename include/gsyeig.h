@@ -90,12 +90,20 @@ typedef struct {
     int64_t guard;         /* extra Ritz vectors carried through the refinement   */
                            /*   (0 = max(8, ceil(s/4)))                           */
     /* both modes */
-    int64_t reorth;        /* full re-orthogonalisation against all of V_k, by   */
+    int64_t reorth;        /* re-orthogonalisation against all of V_k, by        */
                            /*   classical Gram-Schmidt: 0 = two passes every step */
-                           /*   (Sec. 2.3, after Kahan); 1 (default) = the second */
-                           /*   pass only when the first kept less than 1/sqrt(2) */
-                           /*   of the norm (orthogonality monitored and amended, */
-                           /*   the alternative Sec. 2.3 names)                   */
+                           /*   (Sec. 2.3, after Kahan); 1 = the second pass only */
+                           /*   when the first kept less than 1/sqrt(2) of the    */
+                           /*   norm; 2 (default) = partial: the omega recurrence */
+                           /*   estimates w_j^T w_{k+1} on the device, and both   */
+                           /*   passes run only on the steps where an estimate    */
+                           /*   exceeds sqrt(u) and on the step after each (the   */
+                           /*   basis stays semi-orthogonal; the Ritz vectors are */
+                           /*   then made orthonormal by Cholesky QR).  Both 1    */
+                           /*   and 2 monitor orthogonality and amend it, the    */
+                           /*   alternative Sec. 2.3 names.  Block Lanczos always */
+                           /*   orthogonalises each block twice.  Values outside */
+                           /*   0..2 are rejected (-8).                           */
     /* block Lanczos (block > 1) */
     int64_t basis;         /* most basis vectors before a thick restart (0 =     */
                            /*   min(8192, n - block, max(keep + 4 block, 5 s)))   */
@@ -145,6 +153,9 @@ typedef struct {
                            /*   Gram-Schmidt-in-clusters path (diagnostic)      */
     int64_t fallback_reason; /* last one: 1 = two vectors overlapped > 0.5,   */
                            /*   2 = their Gram matrix was not positive definite */
+    int64_t reorth_steps;  /* single-vector Lanczos: steps that ran the         */
+                           /*   conditional Gram-Schmidt (reorth 1: the second  */
+                           /*   pass; 2: both passes; 0: every step)            */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */

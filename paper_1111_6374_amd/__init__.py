@@ -71,7 +71,7 @@ class gsyeig_info(ctypes.Structure):
         ("block_applies", ctypes.c_int64), ("block_cols", ctypes.c_int64), ("restarts", ctypes.c_int64),
         ("basis", ctypes.c_int64), ("kept", ctypes.c_int64), ("t_rr_ms", ctypes.c_double),
         ("rr_count", ctypes.c_int64), ("cluster_fallbacks", ctypes.c_int64),
-        ("fallback_reason", ctypes.c_int64)]
+        ("fallback_reason", ctypes.c_int64), ("reorth_steps", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

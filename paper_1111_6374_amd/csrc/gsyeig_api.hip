@@ -117,7 +117,7 @@ static void opts_fill_defaults(gsyeig_opts *o)
     o->refine_iters = 10;
     o->refine_inner = 20;
     o->guard = 0;
-    o->reorth = 1;
+    o->reorth = 2;
 }
 
 // width of the mixed-mode refinement block: s wanted + guard vectors
@@ -359,10 +359,45 @@ int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64
     return 0;
 }
 
+// Ritz coefficients in an orthonormal basis of span(V_m) when V_m is only
+// semi-orthogonal (partial re-orthogonalisation): with V_m^T V_m = R^T R,
+// W = V_m R^-1 is orthonormal and W^T C W equals T_m up to O(u ||C||)
+// (Simon 1984), so the Ritz vectors are W S = V_m (R^-1 S).  Taking V_m S
+// instead would leave residuals of up to sqrt(u) ||C||: the Gram-Schmidt
+// coefficients of the orthogonalised steps are not part of T_m.  On return
+// S holds R^-1 S; *info_d != 0 if V_m^T V_m was not positive definite.
+static int semiorth_coeffs(gsyeig_ctx *ctx, int64_t n, int64_t m, const double *V, int64_t ldv, double *S,
+                           int64_t nvec, int *info_d)
+{
+    GemmDesc g{};
+    g.m = m; g.n = m; g.k = n;
+    g.A = V; g.lda = ldv; g.a_layout = 1;   // A(i, t) = V(t, i)
+    g.B = V; g.ldb = ldv; g.b_layout = 0;
+    g.c_layout = 1;                         // upper triangle, row-major, as potrf_core reads it
+    g.ldc = m;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.upper_only = 1;
+    const int64_t tiles = cdiv(m, 64) * cdiv(m, 64);
+    g.splitk = (int)std::max<int64_t>(1, std::min<int64_t>({32, 512 / tiles, cdiv(n, 1024)}));
+    const int64_t parts = (g.splitk > 1) ? gemm_splitk_parts(g) : 0;
+    const int64_t mr = cdiv(m, NB) * NB;
+    void *p;
+    TRY(ws_get(ctx, WS_PROG, sizeof(double) * ((size_t)m * m * (1 + parts) + (size_t)mr * NB + 64), &p));
+    double *G = (double *)p, *Dv = G + m * m, *part = Dv + mr * NB;
+    g.C = G;
+    g.part = parts ? part : nullptr;
+    if (!parts) g.splitk = 1;
+    TRY(launch_gemm(g, ctx->stream));
+    TRY(potrf_core(ctx, m, G, m, Dv, info_d));
+    return launch_backsolve(G, m, m, nvec, Dv, S, m, ctx->stream);
+}
+
 struct LzBufs {
     double *z, *tmp, *red, *red2, *h, *normpart, *z0part;
-    int *flag;       // second Gram-Schmidt pass needed (device)
-    int reorth;      // 0: always two passes; 1: second pass when needed
+    int *flag;       // [0] Gram-Schmidt pass needed, [1] count of such steps, [2] next step forced (device)
+    int reorth;      // 0: always two passes; 1: second pass when needed; 2: partial (omega estimates)
+    double *om;      // reorth 2: three omega vectors of length ldom, and the ||T|| estimate after them
+    int64_t ldom;
 };
 
 static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
@@ -381,6 +416,8 @@ static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
     b->flag = (int *)(b->z0part + lz_z0_parts(n));
     b->red2 = b->z0part + lz_z0_parts(n) + 64;
     b->reorth = 1;
+    b->om = nullptr;
+    b->ldom = 0;
     TRY(ws_get(ctx, WS_RED2, sizeof(double) * (size_t)(kmax + 8), &p));
     b->h = (double *)p;
     return 0;
@@ -393,6 +430,20 @@ static int lz_step(gsyeig_ctx *ctx, int64_t n, const LzOp &op, double *V, int64_
     const double *wk = V + k * ldv;
     const double *wp = (k > 0) ? V + (k - 1) * ldv : wk;
     TRY(apply_op(ctx, n, op, wk, b.z, b.tmp, sample));
+    if (b.reorth == 2) {
+        // both passes only on the steps where the omega estimates of w_j^T w_{k+1}
+        // exceed sqrt(u), and on the step after each of them
+        TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream, b.z0part));
+        double *om_c = b.om + (k % 3) * b.ldom, *om_n = b.om + ((k + 1) % 3) * b.ldom;
+        const double *om_p = b.om + ((k + 2) % 3) * b.ldom;
+        TRY(launch_pro_omega(alpha, beta, k, b.z0part, n, om_p, om_c, om_n, b.om + 3 * b.ldom, b.flag,
+                             ctx->stream));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream, b.flag));
+        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream, b.flag));
+        TRY(launch_lz_normalize_sel(b.z, V + (k + 1) * ldv, beta, k, n, b.normpart, b.z0part, b.flag,
+                                    ctx->stream));
+        return 0;
+    }
     if (b.reorth) {
         // second pass only where the first lost more than 1/sqrt(2) of the norm
         TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream, b.z0part));
@@ -415,6 +466,7 @@ static int lz_step(gsyeig_ctx *ctx, int64_t n, const LzOp &op, double *V, int64_
 struct LzResult {
     int64_t steps;
     int64_t nconv;
+    int64_t reorth_steps;
     float t_loop_ms, t_ritz_ms;
 };
 
@@ -438,7 +490,15 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     double *tri = (double *)p;
     LzBufs b;
     TRY(lz_bufs(ctx, n, mmax, &b));
-    b.reorth = o->reorth ? 1 : 0;
+    b.reorth = (int)o->reorth;
+    if (b.reorth == 2) {
+        b.ldom = mmax + 8;
+        TRY(ws_get(ctx, WS_PRO, sizeof(double) * (size_t)(3 * b.ldom + 8), &p));
+        b.om = (double *)p;
+        TRY(launch_pro_init(b.om, b.om + 3 * b.ldom, b.flag, ctx->stream));
+    } else {
+        HIP_TRY(hipMemsetAsync(b.flag, 0, 4 * sizeof(int), ctx->stream));
+    }
     TRY(ctl_reserve(ctx, n));
     int *nconv_d = (int *)ctx->dscal;
     int *nconv_h = (int *)ctx->host_pinned;
@@ -532,6 +592,8 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
         ctx->fallback_why = 1;
         TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
     }
+    if (b.reorth == 2) TRY(semiorth_coeffs(ctx, n, m, V, ldv, S, nvec, oinfo_d + 2));
+    else HIP_TRY(hipMemsetAsync(oinfo_d + 2, 0, sizeof(int), ctx->stream));
     GemmDesc d{};
     d.m = n; d.n = nvec; d.k = m;
     d.A = V; d.lda = ldv; d.a_layout = 0;
@@ -540,8 +602,12 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     d.alpha = 1.0; d.beta = 0.0;
     TRY(launch_gemm_f64(d, ctx->stream));
     TRY(launch_copy(theta, theta_out, nvec, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(nconv_h + 1, b.flag + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(nconv_h + 2, oinfo_d + 2, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    res->reorth_steps = (b.reorth == 0) ? m : nconv_h[1];
+    if (b.reorth == 2 && nconv_h[2] != 0) return GSYEIG_ENOCONV;  // basis lost semi-orthogonality
     TRY(prof_harvest(ctx));
     HIP_TRY(hipEventElapsedTime(&res->t_loop_ms, ctx->ev[6], ctx->ev[7]));
     HIP_TRY(hipEventElapsedTime(&res->t_ritz_ms, ctx->ev[7], ctx->ev[5]));
@@ -796,6 +862,7 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     inf.kept = br.keep;
     inf.t_rr_ms = br.t_rr_ms;
     inf.rr_count = br.rr_count;
+    inf.reorth_steps = r.reorth_steps;
     if (info) *info = inf;
     return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
 }
@@ -968,6 +1035,8 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
         if (blz_check_dims(n, s, nv, &o)) return -8;
         b += blz_bytes(n, s, nv, &o);                                 // block basis, projected matrix
     }
+    if (o.reorth == 2)  // omega estimates, Cholesky QR of the Ritz vectors
+        b += sizeof(double) * (size_t)(3 * (mmax + 8) + 8 + n * s);
     if (o.invert) {
         b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
         if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
@@ -1118,7 +1187,7 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
     if (ldy < n) return -11;
     gsyeig_opts o;
     if (opts) o = *opts; else opts_fill_defaults(&o);
-    if (o.prec != GSYEIG_FP64 || o.block < 1 || o.invert) return -8;
+    if (o.prec != GSYEIG_FP64 || o.block < 1 || o.invert || o.reorth < 0 || o.reorth > 2) return -8;
     if (o.block > 1) TRY(blz_check_dims(n, s, s, &o));
     double *Dinv;
     TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
@@ -1196,6 +1265,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (opts) o = *opts; else opts_fill_defaults(&o);
     if (!o.invert) ctx->n_fallback = ctx->fallback_why = 0;
     if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block < 1 || (o.invert != 0 && o.invert != 1) ||
+        o.reorth < 0 || o.reorth > 2 ||
         (o.which != 0 && o.which != 1))
         return -8;
     if (o.block > 1) TRY(blz_check_dims(n, s, o.prec == GSYEIG_MIXED ? mixed_block(n, s, &o) : s, &o));
@@ -1284,6 +1354,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.kept = br.keep;
     inf.t_rr_ms = br.t_rr_ms;
     inf.rr_count = br.rr_count;
+    inf.reorth_steps = r.reorth_steps;
     inf.cluster_fallbacks = ctx->n_fallback;
     inf.fallback_reason = ctx->fallback_why;
     if (info) *info = inf;

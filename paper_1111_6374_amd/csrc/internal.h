@@ -65,6 +65,8 @@ enum WsSlot {
     WS_BLZ,        // block Lanczos: projected matrix, Ritz coefficients, blocks, kept Ritz vectors
     WS_SYMVFUSE,   // tile queue of the fused KI1 + KI2 sweep
     WS_FUSE3,      // tile queue and sentinel partials of the fused KI2 + KI3 sweep
+    WS_PRO,        // omega estimates of the partial re-orthogonalisation (3 x (max_steps + 2))
+    WS_PROG,       // Gram matrix V_m^T V_m of the semi-orthogonal basis and its Cholesky data
     WS_COUNT
 };
 
@@ -214,6 +216,13 @@ int lz_z0_parts(int64_t n);
 int launch_reorth_flag(const double *z0part, int64_t n, const double *z1part, int *flag, hipStream_t st);
 int launch_lz_normalize(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
                         const double *normpart, hipStream_t st);
+// partial re-orthogonalisation: omega recurrence and the decision flag
+// flag: [0] orthogonalise this step, [1] count of such steps, [2] force next
+int launch_pro_init(double *om0, double *anorm, int *flag, hipStream_t st);
+int launch_pro_omega(const double *alpha, const double *beta, int64_t k, const double *z0part, int64_t n,
+                     const double *omP, const double *omC, double *omN, double *anorm, int *flag, hipStream_t st);
+int launch_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
+                            const double *normpart, const double *z0part, const int *flag, hipStream_t st);
 
 // tridiagonal eigensolver (KI5)
 int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_t nwant, int which,

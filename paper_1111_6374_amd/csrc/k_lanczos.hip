@@ -139,13 +139,18 @@ __global__ __launch_bounds__(256) void k_lz_sub_alpha(double *z, const double *w
 // Second Gram-Schmidt pass needed?  (Kahan's test as used by Parlett: a
 // pass that keeps at least 1/sqrt(2) of the norm leaves z orthogonal to V to
 // working accuracy.)  flag = 1 if ||z1||^2 < ||z0||^2 / 2.
+// flag[1] counts the steps that took the second pass.
 __global__ __launch_bounds__(256) void k_reorth_flag(const double *z0part, int P0, const double *z1part, int P1,
                                                      int *flag)
 {
     __shared__ double sbuf[4];
     const double a = sum_parts(z0part, P0, sbuf);
     const double b = sum_parts(z1part, P1, sbuf);
-    if (threadIdx.x == 0) *flag = (b < 0.5 * a) ? 1 : 0;
+    if (threadIdx.x == 0) {
+        const int f = (b < 0.5 * a) ? 1 : 0;
+        flag[0] = f;
+        flag[1] += f;
+    }
 }
 
 // Gram-Schmidt projection, stage 1: part[rc * kcols + c] = V(rows of rc, c)^T z(rows of rc)
@@ -257,9 +262,115 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *w
     if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
 }
 
+// Partial re-orthogonalisation (Simon 1984; Sec. 2.3's "monitor the
+// orthogonality and amend it when lost"): omega_j,k estimates w_j^T w_k.  From
+// the Lanczos relation beta_k w_{k+1} = C w_k - alpha_k w_k - beta_{k-1} w_{k-1}
+// and the same relation for w_j,
+//   beta_k om_{j,k+1} = beta_j om_{j+1,k} + (alpha_j - alpha_k) om_{j,k}
+//                       + beta_{j-1} om_{j-1,k} - beta_{k-1} om_{j,k-1} + rounding,
+// with om_{k,k} = 1 and om_{k,k+1} at rounding level.  The rounding terms are
+// bounded by eps1 ||T||, eps1 = sqrt(n) u / 2, added with the sign of the sum
+// (the usual pessimistic choice).  When max_j |om_{j,k+1}| exceeds sqrt(u),
+// z is orthogonalised against all of V (two passes) at this step and the
+// next one (the first pass leaves the next vector's estimate unreliable),
+// and the estimates restart at eps1.  omN[j] = om_{j,k+1}, omC = om_{.,k},
+// omP = om_{.,k-1}; beta_k is taken from the unorthogonalised z (z0part).
+// flag[0] = this step orthogonalises, flag[1] counts such steps, flag[2] =
+// the next step must orthogonalise; *anorm = running estimate of ||T||.
+__global__ __launch_bounds__(256) void k_pro_omega(const double *alpha, const double *beta, int64_t k,
+                                                   const double *z0part, int P0, const double *omP,
+                                                   const double *omC, double *omN, double *anorm, int *flag,
+                                                   double eps1)
+{
+    __shared__ double sbuf[4];
+    __shared__ double s_mx[256];
+    const double bk = sqrt(sum_parts(z0part, P0, sbuf));
+    const double ak = alpha[k];
+    const double bkm1 = (k > 0) ? beta[k - 1] : 0.0;
+    const double an = fmax(*anorm, fabs(ak) + bk + bkm1);
+    const double tau = eps1 * an;
+    const double inv = (bk > 0.0) ? 1.0 / bk : 0.0;
+    double mx = 0.0;
+    for (int64_t j = threadIdx.x; j < k; j += 256) {
+        double num = beta[j] * omC[j + 1] + (alpha[j] - ak) * omC[j] - bkm1 * omP[j];
+        if (j > 0) num += beta[j - 1] * omC[j - 1];
+        const double o = (num + copysign(tau, num)) * inv;
+        omN[j] = o;
+        mx = fmax(mx, fabs(o));
+    }
+    s_mx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s_mx[threadIdx.x] = fmax(s_mx[threadIdx.x], s_mx[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const int forced = flag[2];
+    // sqrt(u) = 2^-26.5, with u = 2^-53.  A small beta_k (near breakdown) also
+    // loses local orthogonality, om_{k,k+1} = tau / beta_k: orthogonalise then.
+    constexpr double thr = 1.0536712127723509e-08;
+    const int f = forced || !(s_mx[0] <= thr) || (bk * thr < tau);
+    if (f)  // the two passes restore orthogonality to working accuracy
+        for (int64_t j = threadIdx.x; j < k; j += 256) omN[j] = eps1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        omN[k] = f ? eps1 : tau * inv;
+        omN[k + 1] = 1.0;
+        *anorm = an;
+        flag[0] = f;
+        flag[1] += f;
+        flag[2] = f && !forced;
+    }
+}
+
+__global__ void k_pro_init(double *om0, double *anorm, int *flag)
+{
+    if (threadIdx.x == 0) {
+        om0[0] = 1.0;
+        *anorm = 0.0;
+        flag[0] = flag[1] = flag[2] = 0;
+    }
+}
+
+// beta_k = sqrt(sum of the norm partials of the orthogonalised z (flag set)
+// or of the unorthogonalised z); w_{k+1} := z / beta_k
+__global__ __launch_bounds__(256) void k_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k,
+                                                          int64_t n, const double *normpart, int P,
+                                                          const double *z0part, int P0, const int *flag)
+{
+    __shared__ double sbuf[4];
+    const bool f = *flag != 0;
+    const double b = sqrt(f ? sum_parts(normpart, P, sbuf) : sum_parts(z0part, P0, sbuf));
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) wnext[i] = z[i] / b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
+}
+
 inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
 
 }  // namespace
+
+int launch_pro_init(double *om0, double *anorm, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pro_init, dim3(1), dim3(64), 0, st, om0, anorm, flag);
+    return ok();
+}
+
+int launch_pro_omega(const double *alpha, const double *beta, int64_t k, const double *z0part, int64_t n,
+                     const double *omP, const double *omC, double *omN, double *anorm, int *flag, hipStream_t st)
+{
+    const double eps1 = 0.5 * sqrt((double)n) * 0x1p-53;
+    hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(256), 0, st, alpha, beta, k, z0part, lz_z0_parts(n), omP, omC,
+                       omN, anorm, flag, eps1);
+    return ok();
+}
+
+int launch_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
+                            const double *normpart, const double *z0part, const int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_normalize_sel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wnext, beta, k, n,
+                       normpart, lz_norm_parts(n), z0part, lz_z0_parts(n), flag);
+    return ok();
+}
 
 int lz_red_parts(int64_t n) { return (int)cdiv(n, RB); }
 int lz_norm_parts(int64_t n) { return (int)cdiv(n, 64); }

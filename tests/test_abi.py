@@ -53,7 +53,7 @@ def test_version_and_defaults(gs):
     assert o.tol == 1e-12 and o.check_every == 25 and o.seed == 6374 and not o.v0
     assert ctypes.sizeof(gs.gsyeig_opts) == 128 and o.profile_every == 0
     assert (o.basis, o.keep, o.block_acc32) == (0, 0, 0)
-    assert (o.eta_tol, o.refine_iters, o.refine_inner, o.guard, o.reorth) == (1e-10, 10, 20, 0, 1)
+    assert (o.eta_tol, o.refine_iters, o.refine_inner, o.guard, o.reorth) == (1e-10, 10, 20, 0, 2)
 
 
 def test_workspace_size(gs):
