@@ -430,3 +430,20 @@ def test_syev_small_gram_like_cluster(gs, ctx, torch, orc, N, nwant, width):
     assert np.max(np.abs(w - np.sort(w_true)[:nwant])) <= 50 * N * U64
     assert np.linalg.norm(V.T @ V - np.eye(nwant)) <= 100 * N * U64
     assert np.linalg.norm(H @ V - V * w[None, :]) <= 100 * N * U64
+
+
+@pytest.mark.parametrize("n,lda", [(700, 704), (1000, 1024), (4100, 4160), (1000, 1004), (1002, 1002), (999, 1001)])
+def test_symv_lp_leading_dimension(gs, ctx, torch, orc, n, lda):
+    """FP32 SYMV with a padded leading dimension: the 16-byte-load kernel
+    (lda, n multiples of 4), the 8-byte one (lda even) and the scalar one."""
+    say("symv_lp ld", n, lda)
+    A = f32(gen.random_symmetric(n, stream=(35, n)))
+    Ap = np.full((n, lda), np.nan, dtype=np.float32)   # padding is never read
+    Ap[:, :n] = A
+    x = gen.rng(gen.BASE_SEED, 36, n).standard_normal(n)
+    yd = torch.zeros(n, dtype=torch.float64, device="cuda")
+    assert gs.gsyeig_symv_lp(ctx, n, torch.from_numpy(Ap).cuda(), lda, dev(torch, x), yd) == 0
+    y = host(yd)
+    ref = orc.matvec(A, x)
+    bound = 4 * n * U64 * (np.abs(A) @ np.abs(x))
+    assert np.all(np.abs(y - ref) <= bound + 1e-300)
