@@ -26,28 +26,39 @@ __global__ __launch_bounds__(256) void k_potrf_diag(T *B, int64_t ldb, int64_t n
         a[i][j] = (i < r && j < r && j >= i) ? (double)B[(r0 + i) * ldb + r0 + j] : 0.0;
         x[i][j] = 0.0;
     }
-    __syncthreads();
+    __shared__ double s_d[NB];
+    // Right-looking on unscaled rows (the LDL^T form): step j subtracts
+    // a_ji a_jl / p_j from a_il (j < i <= l), p_j = a_jj; row j is scaled by
+    // 1 / sqrt(p_j) at the end.  Thread (g, l) = (tid >> 6, tid & 63) updates
+    // column l in rows i = j + 1 + g, + 4, ...; one barrier per step.
+    const int l = tid & 63, g = tid >> 6;
     for (int j = 0; j < r; ++j) {
-        if (tid == 0) {
-            double p = a[j][j];
-            if (!(p > 0.0)) {
-                atomicCAS(info, 0, (int)(r0 + j + 1));
-                p = 1.0;
-            }
-            a[j][j] = sqrt(p);
+        __syncthreads();
+        double p = a[j][j];
+        if (!(p > 0.0)) p = 1.0;  // recorded below; the sweep continues without NaNs
+        if (l > j && l < r) {
+            const double f = a[j][l] / p;
+            for (int i = j + 1 + g; i <= l; i += 4) a[i][l] -= a[j][i] * f;
         }
-        __syncthreads();
-        const double d = a[j][j];
-        for (int l = j + 1 + tid; l < r; l += 256) a[j][l] /= d;
-        __syncthreads();
-        // a[i][l] -= a[j][i] a[j][l] for j < i <= l < r
-        const int m = r - j - 1;
-        for (int t = tid; t < m * m; t += 256) {
-            const int i = j + 1 + t / m, l = j + 1 + t % m;
-            if (l >= i) a[i][l] -= a[j][i] * a[j][l];
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (tid < 64) {
+        double p = (tid < r) ? a[tid][tid] : 1.0;
+        const bool bad = !(p > 0.0);
+        if (bad) p = 1.0;
+        s_d[tid] = sqrt(p);
+        // the first non-positive pivot of the block (blocks run in order)
+        const unsigned long long m = __ballot(bad);
+        if (tid == 0 && m) atomicCAS(info, 0, (int)(r0 + __ffsll((long long)m)));
+    }
+    __syncthreads();
+    for (int t = tid; t < NB * NB; t += 256) {
+        const int i = t >> 6, c = t & 63;
+        if (i < r && c < r && c > i) a[i][c] /= s_d[i];
+    }
+    __syncthreads();
+    if (tid < r) a[tid][tid] = s_d[tid];
+    __syncthreads();
     // inverse of the upper-triangular block, one column per thread
     if (tid < r) {
         const int j = tid;

@@ -191,6 +191,95 @@ __global__ __launch_bounds__(256) void k_symv_tiles_f32(const float *__restrict_
     }
 }
 
+// FP64 A with lda and n even: 16-byte loads of column pairs.  Lane ->
+// columns cp = 2 (lane & 31), cp + 1 of a tile and row group rg = 2 w +
+// (lane >> 5) (rows rg + 8 q, q < 8), so one wave instruction reads two whole
+// 512-byte tile rows.  Row parts are summed inside the wave, column parts of
+// the four waves meet once in LDS in a fixed order; x_J is staged in LDS.
+// Loads come from clamped in-bounds addresses and are masked by bits (with
+// n even a column pair is wholly inside or wholly outside the matrix).
+template <int CH>
+__global__ __launch_bounds__(256) void k_symv_tiles_q(const double *__restrict__ A, int64_t lda, int64_t n,
+                                                      int nblk, int maxch, const double *__restrict__ x,
+                                                      const int2 *__restrict__ items, double *__restrict__ Pr,
+                                                      double *__restrict__ Pc)
+{
+    __shared__ double s_x[CH * NB];
+    __shared__ double s_col[CH][4][NB];
+    __shared__ double s_row[NB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int2 it = items[blockIdx.x];
+    const int I = it.x, J0 = it.y;
+    const int J1 = (J0 + CH < nblk) ? J0 + CH : nblk;
+    const int64_t r0 = (int64_t)I * NB;
+    const int cp = 2 * (lane & 31);
+    const int rg = 2 * w + (lane >> 5);
+    double2 a[CH][8];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        const int64_t col = (int64_t)(J0 + t) * NB + cp;
+        const bool cok = (J0 + t < J1) && col < n;
+        const int64_t cc = cok ? col : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t row = r0 + rg + 8 * q;
+            const unsigned long long m = (cok && row < n) ? ~0ull : 0ull;
+            const double2 v = *reinterpret_cast<const double2 *>(A + (row < n ? row : 0) * lda + cc);
+            a[t][q].x = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.x) & m));
+            a[t][q].y = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.y) & m));
+        }
+    }
+    for (int e = tid; e < CH * NB; e += 256) {
+        const int64_t col = (int64_t)J0 * NB + e;
+        s_x[e] = (J0 + e / NB < J1 && col < n) ? x[col] : 0.0;
+    }
+    double xi[8], acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t row = r0 + rg + 8 * q;
+        xi[q] = (row < n) ? x[row] : 0.0;
+        acc[q] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        const double x0 = s_x[t * NB + cp], x1 = s_x[t * NB + cp + 1];
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc[q] = fma(a[t][q].y, x1, fma(a[t][q].x, x0, acc[q]));
+            c0 = fma(a[t][q].x, xi[q], c0);
+            c1 = fma(a[t][q].y, xi[q], c1);
+        }
+        c0 += __shfl_xor(c0, 32);
+        c1 += __shfl_xor(c1, 32);
+        if (lane < 32) {
+            s_col[t][w][cp] = c0;
+            s_col[t][w][cp + 1] = c1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double v = acc[q];
+        for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o);
+        acc[q] = v;
+    }
+    if ((lane & 31) == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s_row[rg + 8 * q] = acc[q];
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int ch = (J0 - I) / CH;
+        Pr[((int64_t)I * maxch + ch) * NB + tid] = s_row[tid];
+    }
+    for (int e = tid; e < CH * NB; e += 256) {
+        const int t = e / NB, c = e % NB, J = J0 + t;
+        if (J < J1 && J > I)
+            Pc[((int64_t)J * nblk + I) * NB + c] = (s_col[t][0][c] + s_col[t][1][c]) + (s_col[t][2][c] + s_col[t][3][c]);
+    }
+}
+
 // The same product with A stored FP32, lda and n multiples of 4: 16-byte
 // loads.  Lane -> column quad cl = 4 (lane & 15) of a tile and row group
 // rg = 4 w + (lane >> 4) (rows rg + 16 q, q < 4), so one wave instruction
@@ -357,10 +446,16 @@ static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, co
     if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &pc))) return rc;
     const int2 *items = (const int2 *)ctx->ws[WS_SYMVMAP];
     const dim3 grid((unsigned)ctx->symv_items);
-    if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_symv_tiles, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
-                           (double *)pr, (double *)pc);
-    else if (quad)
+    if constexpr (sizeof(T) == 8) {
+        // 16-byte column pairs when rows and n are even (measured 0.203 ms
+        // against 0.230 ms for the 8-byte kernel at n = 16384, MI355X)
+        if (lda % 2 == 0 && n % 2 == 0)
+            hipLaunchKernelGGL(k_symv_tiles_q<SYMV_CH>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x,
+                               items, (double *)pr, (double *)pc);
+        else
+            hipLaunchKernelGGL(k_symv_tiles, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
+                               (double *)pr, (double *)pc);
+    } else if (quad)
         hipLaunchKernelGGL(k_symv_tiles_f32q<SYMV_CH>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
                            (double *)pr, (double *)pc);
     else if (lda % 2 == 0)

@@ -54,18 +54,38 @@ __device__ void gershgorin(const double *alpha, const double *beta, int64_t m, d
     *pivmin = 0x1p-1022 * fmax(1.0, wave_max(b2));
 }
 
-// number of eigenvalues of T below sigma (LDL^T pivots of T - sigma I)
+__device__ __forceinline__ void sturm_step(double a, double b2, double sigma, double pivmin, double &q, int &cnt)
+{
+    q = (a - sigma) - b2 / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+}
+
+// number of eigenvalues of T below sigma (LDL^T pivots of T - sigma I), one
+// sigma per lane.  alpha_j and beta_{j-1}^2 come in chunks of 64 rows, one
+// row per lane, read back with readlane; the next chunk's loads are in
+// flight while a chunk is processed, so the recurrence never waits on
+// memory.  (Row 0 has b2 = 0, so its pivot is alpha_0 - sigma.)
 __device__ int sturm_count(const double *alpha, const double *beta, int64_t m, double sigma,
                            double pivmin)
 {
-    double q = alpha[0] - sigma;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0;
-    for (int64_t j = 1; j < m; ++j) {
-        const double b = beta[j - 1];
-        q = (alpha[j] - sigma) - (b * b) / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
+    const int lane = threadIdx.x & 63;
+    double an = (lane < m) ? alpha[lane] : 0.0;
+    double bn = (lane >= 1 && lane < m) ? beta[lane - 1] * beta[lane - 1] : 0.0;
+    double q = 1.0;
+    int cnt = 0;
+    for (int64_t j0 = 0; j0 < m; j0 += 64) {
+        const double ac = an, bc = bn;
+        const int64_t jn = j0 + 64 + lane;
+        an = (jn < m) ? alpha[jn] : 0.0;
+        bn = (jn < m) ? beta[jn - 1] * beta[jn - 1] : 0.0;
+        if (m - j0 >= 64) {
+#pragma unroll
+            for (int t = 0; t < 64; ++t) sturm_step(rdlane(ac, t), rdlane(bc, t), sigma, pivmin, q, cnt);
+        } else {
+            const int c = (int)(m - j0);
+            for (int t = 0; t < c; ++t) sturm_step(rdlane(ac, t), rdlane(bc, t), sigma, pivmin, q, cnt);
+        }
     }
     return cnt;
 }
