@@ -29,6 +29,7 @@ __device__ __noinline__ double settle_slow(unsigned long long v, const double *p
             __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return 0.0;
         }
+        __builtin_amdgcn_s_sleep(2);  // fewer polls on lines every waiting workgroup reads
         v = ld_bits(p);
     }
     return __longlong_as_double((long long)v);

@@ -93,17 +93,18 @@ __global__ __launch_bounds__(256) void k_scale_by_norm(const double *v, double *
     if (norm_out && blockIdx.x == 0 && threadIdx.x == 0) *norm_out = nrm;
 }
 
-// z := z - beta_{k-1} w_{k-1} (k > 0); part = w_k . z
+// z := z - beta_{k-1} w_{k-1} (k > 0); part = w_k . z over chunks of R rows
+template <int R>
 __global__ __launch_bounds__(256) void k_lz_three_term(double *z, const double *wprev,
                                                        const double *wk, const double *beta,
                                                        int64_t k, int64_t n, double *part)
 {
     __shared__ double sbuf[4];
     const double bp = (k > 0) ? beta[k - 1] : 0.0;
-    const int64_t base = (int64_t)blockIdx.x * RB;
+    const int64_t base = (int64_t)blockIdx.x * R;
     double v = 0.0;
 #pragma unroll
-    for (int p = 0; p < RB / 256; ++p) {
+    for (int p = 0; p < R / 256; ++p) {
         const int64_t i = base + threadIdx.x + 256 * p;
         if (i < n) {
             double zi = z[i];
@@ -277,42 +278,52 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *w
 // omP = om_{.,k-1}; beta_k is taken from the unorthogonalised z (z0part).
 // flag[0] = this step orthogonalises, flag[1] counts such steps, flag[2] =
 // the next step must orthogonalise; *anorm = running estimate of ||T||.
-__global__ __launch_bounds__(256) void k_pro_omega(const double *alpha, const double *beta, int64_t k,
-                                                   const double *z0part, int P0, const double *omP,
-                                                   const double *omC, double *omN, double *anorm, int *flag,
-                                                   double eps1)
+__global__ __launch_bounds__(1024) void k_pro_omega(const double *alpha, const double *beta, int64_t k,
+                                                    const double *z0part, int P0, const double *omP,
+                                                    const double *omC, double *omN, double *anorm, int *flag,
+                                                    double eps1)
 {
-    __shared__ double sbuf[4];
-    __shared__ double s_mx[256];
-    const double bk = sqrt(sum_parts(z0part, P0, sbuf));
+    __shared__ double s_red[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // beta_k before any orthogonalisation: sum of the partials, fixed order
+    double v = 0.0;
+    for (int p = tid; p < P0; p += 1024) v += z0part[p];
+    v = wave_sum(v);
+    if (lane == 0) s_red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += s_red[w];
+    const double bk = sqrt(t);
     const double ak = alpha[k];
     const double bkm1 = (k > 0) ? beta[k - 1] : 0.0;
     const double an = fmax(*anorm, fabs(ak) + bk + bkm1);
     const double tau = eps1 * an;
     const double inv = (bk > 0.0) ? 1.0 / bk : 0.0;
     double mx = 0.0;
-    for (int64_t j = threadIdx.x; j < k; j += 256) {
+    for (int64_t j = tid; j < k; j += 1024) {
         double num = beta[j] * omC[j + 1] + (alpha[j] - ak) * omC[j] - bkm1 * omP[j];
         if (j > 0) num += beta[j - 1] * omC[j - 1];
         const double o = (num + copysign(tau, num)) * inv;
         omN[j] = o;
         mx = fmax(mx, fabs(o));
     }
-    s_mx[threadIdx.x] = mx;
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) s_mx[threadIdx.x] = fmax(s_mx[threadIdx.x], s_mx[threadIdx.x + h]);
-        __syncthreads();
-    }
+    if (lane == 0) s_red[wv] = mx;
+    __syncthreads();
+    mx = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) mx = fmax(mx, s_red[w]);
     const int forced = flag[2];
     // sqrt(u) = 2^-26.5, with u = 2^-53.  A small beta_k (near breakdown) also
     // loses local orthogonality, om_{k,k+1} = tau / beta_k: orthogonalise then.
     constexpr double thr = 1.0536712127723509e-08;
-    const int f = forced || !(s_mx[0] <= thr) || (bk * thr < tau);
+    const int f = forced || !(mx <= thr) || (bk * thr < tau);
     if (f)  // the two passes restore orthogonality to working accuracy
-        for (int64_t j = threadIdx.x; j < k; j += 256) omN[j] = eps1;
+        for (int64_t j = tid; j < k; j += 1024) omN[j] = eps1;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         omN[k] = f ? eps1 : tau * inv;
         omN[k + 1] = 1.0;
         *anorm = an;
@@ -359,7 +370,7 @@ int launch_pro_omega(const double *alpha, const double *beta, int64_t k, const d
                      const double *omP, const double *omC, double *omN, double *anorm, int *flag, hipStream_t st)
 {
     const double eps1 = 0.5 * sqrt((double)n) * 0x1p-53;
-    hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(256), 0, st, alpha, beta, k, z0part, lz_z0_parts(n), omP, omC,
+    hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(1024), 0, st, alpha, beta, k, z0part, lz_z0_parts(n), omP, omC,
                        omN, anorm, flag, eps1);
     return ok();
 }
@@ -401,8 +412,14 @@ int launch_normalize_into(const double *v, double *w, int64_t n, double *part, d
 int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *alpha,
                     const double *beta, int64_t k, int64_t n, double *part, hipStream_t st, double *z0part)
 {
-    const int P = lz_red_parts(n);
-    hipLaunchKernelGGL(k_lz_three_term, dim3(P), dim3(256), 0, st, z, wprev, wk, beta, k, n, part);
+    // 512-row chunks (enough workgroups to stream the three vectors) while
+    // the partials fit the 1024 slots; 2048-row chunks beyond
+    const bool small = n <= 512 * 1024;
+    const int P = (int)cdiv(n, small ? 512 : RB);
+    if (small)
+        hipLaunchKernelGGL(k_lz_three_term<512>, dim3(P), dim3(256), 0, st, z, wprev, wk, beta, k, n, part);
+    else
+        hipLaunchKernelGGL(k_lz_three_term<RB>, dim3(P), dim3(256), 0, st, z, wprev, wk, beta, k, n, part);
     if (ok()) return GSYEIG_EHIP;
     hipLaunchKernelGGL(k_lz_sub_alpha, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wk, alpha,
                        k, n, (const double *)part, P, z0part);

@@ -25,6 +25,7 @@
 #define TPS 8          // tiles per super-block
 #define SBR (TPS * NB) // super-block rows
 #define GRP 8          // far tiles per poll round (a whole super-block)
+#define LG 4           // tiles per round of the double-buffered KI1 sweep
 
 namespace {
 
@@ -163,69 +164,69 @@ __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int6
             y[r] = fma(Uinv[(int64_t)S * SBR * SBR + (int64_t)(rowl + r) * SBR + c * NB + l], bv, y[r]);
     }
 
-    // far tiles: j = nblk-1 down to (S+2)*TPS, subtracted from y as they arrive
-    const int jlo = (S + 2) * TPS;
-    const int ntile = nblk - jlo;
-    if (ntile > 0) {
+    // Every tile right of the super-block, from the last one (j = nblk-1) to
+    // the first of S+1 (the link), subtracted from y as its x values arrive:
+    // rounds of LG tiles, double-buffered, so a round's W values are in
+    // flight while the previous round waits for its x values.  The link
+    // tiles are simply the last rounds, and their W values are resident by
+    // the time x_{S+1} is published.  Each round's polls are issued before
+    // the next round's loads (loads complete in order).
+    const int NT = has_next ? nblk - (S + 1) * TPS : 0;
+    if (NT > 0) {
         const T *Wr = W + (r0 + 4 * w) * ldw;  // rows of a tile before the last super-block exist
         const int64_t cmax = n - 1;
+        const int jdum = (S + 1) * TPS;
         auto colof = [&](int t) {
-            const int j = (t < ntile) ? nblk - 1 - t : jlo;
+            const int j = (t < NT) ? nblk - 1 - t : jdum;
             const int64_t cc = (int64_t)j * NB + l;
             return cc < cmax ? cc : cmax;
         };
-        // one round per GRP tiles: the tiles' W values and the polls of their
-        // x values are all in flight together
-        for (int t0 = 0; t0 < ntile; t0 += GRP) {
-            double cur[GRP][4];
+        double cur[LG][4], nxt[LG][4];
 #pragma unroll
-            for (int g = 0; g < GRP; ++g) {
-                const int64_t cc = colof(t0 + g);
+        for (int g = 0; g < LG; ++g) {
+            const int64_t cc = colof(g);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cur[g][r] = (double)Wr[(int64_t)r * ldw + cc];
+            for (int r = 0; r < 4; ++r) cur[g][r] = (double)Wr[(int64_t)r * ldw + cc];
+        }
+        // wave 0 alone polls a round's x values and hands them to the other
+        // waves through LDS (two slots, one barrier per round): sixteen times
+        // fewer polls on the staging lines every workgroup is waiting for
+        __shared__ double s_xr[2][LG * NB];
+        for (int t0 = 0, rnd = 0; t0 < NT; t0 += LG, ++rnd) {
+            unsigned long long v[LG];
+            if (w == 0) {
+#pragma unroll
+                for (int g = 0; g < LG; ++g) v[g] = ld_bits(stage + colof(t0 + g));
             }
-            unsigned long long v[GRP];
+            if (t0 + LG < NT) {
 #pragma unroll
-            for (int g = 0; g < GRP; ++g) v[g] = ld_bits(stage + colof(t0 + g));
+                for (int g = 0; g < LG; ++g) {
+                    const int64_t cc = colof(t0 + LG + g);
 #pragma unroll
-            for (int g = 0; g < GRP; ++g) {
-                const int t = t0 + g;
-                const int64_t col = (int64_t)(nblk - 1 - t) * NB + l;
-                const bool live = (t < ntile) && (col < n);
-                const double xv = live ? settle(v[g], stage + colof(t), &ctl->err) : 0.0;
+                    for (int r = 0; r < 4; ++r) nxt[g][r] = (double)Wr[(int64_t)r * ldw + cc];
+                }
+            }
+            double *sx = s_xr[rnd & 1];
+            if (w == 0) {
+#pragma unroll
+                for (int g = 0; g < LG; ++g) {
+                    const int t = t0 + g;
+                    const int64_t col = (int64_t)(nblk - 1 - t) * NB + l;
+                    const bool live = (t < NT) && (col < n);
+                    sx[g * NB + l] = live ? settle(v[g], stage + colof(t), &ctl->err) : 0.0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < LG; ++g) {
+                const double xv = sx[g * NB + l];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) y[r] = fma(-cur[g][r], xv, y[r]);
             }
-        }
-    }
-
-    // the link: rows of W_{S,S+1} (loaded before x_{S+1} can arrive), x_{S+1}.
-    // Wave-uniform row pointers and 32-bit lane offsets keep the 32
-    // prefetched values and their addresses within the register budget.
-    if (has_next) {
-        const int64_t k1 = s0 + SBR;                     // first column of S+1
-        const int lim = (int)(n - 1 - k1);               // last valid offset in S+1
-        const T *Wl[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Wl[r] = W + (r0 + 4 * w + r) * ldw + k1;
-        const double *sl = stage + k1;
-        double nr[TPS][4];
+            for (int g = 0; g < LG; ++g)
 #pragma unroll
-        for (int c = 0; c < TPS; ++c) {
-            const int o = min(c * NB + l, lim);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) nr[c][r] = (double)Wl[r][o];
-        }
-        unsigned long long v[TPS];
-#pragma unroll
-        for (int c = 0; c < TPS; ++c) v[c] = ld_bits(sl + min(c * NB + l, lim));
-#pragma unroll
-        for (int c = 0; c < TPS; ++c) {
-            const int o = c * NB + l;
-            const double xv = settle(v[c], sl + min(o, lim), &ctl->err);
-            const double xn = (o <= lim) ? xv : 0.0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) y[r] = fma(-nr[c][r], xn, y[r]);
+                for (int r = 0; r < 4; ++r) cur[g][r] = nxt[g][r];
         }
     }
 #pragma unroll
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
     __shared__ double s_sp[SYMV ? 4 : 1][4][NB];
     __shared__ double s_b[SYMV ? 16 : 1][NB];
     __shared__ int s_q[4];   // ticket, queue exhausted, ready flag
+    __shared__ double s_y[SBR];  // y values of a super-block, polled once per workgroup
     double *stage = ctl_stage(ctl);  // holds y
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     if (tid == 0) {
@@ -433,12 +435,19 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
         for (int c = 0; c < TPS; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) nr[c][r] = WLt[(int64_t)S * SBR * SBR + (int64_t)(al + r) * SBR + c * NB + l];
-        unsigned long long v[TPS];
+        // y_{S-1}: polled by wave 0 alone, handed over through LDS
+        if (w == 0) {
+            unsigned long long v[TPS];
 #pragma unroll
-        for (int c = 0; c < TPS; ++c) v[c] = ld_bits(stage + s0 - SBR + (int64_t)c * NB + l);
+            for (int c = 0; c < TPS; ++c) v[c] = ld_bits(stage + s0 - SBR + (int64_t)c * NB + l);
+#pragma unroll
+            for (int c = 0; c < TPS; ++c)
+                s_y[c * NB + l] = settle(v[c], stage + s0 - SBR + (int64_t)c * NB + l, &ctl->err);
+        }
+        __syncthreads();
 #pragma unroll
         for (int c = 0; c < TPS; ++c) {
-            const double yp = settle(v[c], stage + s0 - SBR + (int64_t)c * NB + l, &ctl->err);
+            const double yp = s_y[c * NB + l];
 #pragma unroll
             for (int r = 0; r < 4; ++r) lk[r] = fma(nr[c][r], yp, lk[r]);
         }
@@ -466,18 +475,25 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
     // x rows of this tile: Uinv_SS^T[al + r][k] y_S[k], k <= al + r (chunks c <= loc);
     // y_S is published by the tiles of S (this one included), polled together
     {
-        unsigned long long rb[TPS];
+        // polled by wave 0 alone, handed over through LDS (the link's slot
+        // is free: every wave has passed the barrier above since reading it)
+        if (w == 0) {
+            unsigned long long rb[TPS];
 #pragma unroll
-        for (int c = 0; c < TPS; ++c) {
-            const int64_t kk = s0 + (int64_t)c * NB + l;
-            rb[c] = ld_bits(stage + (kk < n ? kk : n - 1));
+            for (int c = 0; c < TPS; ++c) {
+                const int64_t kk = s0 + (int64_t)c * NB + l;
+                rb[c] = ld_bits(stage + (kk < n ? kk : n - 1));
+            }
+#pragma unroll
+            for (int c = 0; c < TPS; ++c) {
+                const int64_t kk = s0 + (int64_t)c * NB + l;
+                s_y[c * NB + l] = (c <= loc && kk < n) ? settle(rb[c], stage + kk, &ctl->err) : 0.0;
+            }
         }
+        __syncthreads();
         double rv[TPS];
 #pragma unroll
-        for (int c = 0; c < TPS; ++c) {
-            const int64_t kk = s0 + (int64_t)c * NB + l;
-            rv[c] = (c <= loc && kk < n) ? settle(rb[c], stage + kk, &ctl->err) : 0.0;
-        }
+        for (int c = 0; c < TPS; ++c) rv[c] = s_y[c * NB + l];
         double xo[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int c = 0; c < TPS; ++c) {
