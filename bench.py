@@ -159,6 +159,8 @@ def main():
     opts.profile_every = args.profile_every
     if args.reorth >= 0:
         opts.reorth = args.reorth
+    if args.block > 1:
+        opts.block = args.block
     Lam = torch.empty(s, dtype=torch.float64, device=dev)
     X = torch.empty(s, n, dtype=torch.float64, device=dev)
 
@@ -214,7 +216,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "fp64",
-                   "block": 1, "lanczos_steps": int(last.steps), "reorth": int(opts.reorth),
+                   "block": int(opts.block), "lanczos_steps": int(last.steps), "reorth": int(opts.reorth),
                    "reorth_steps": int(last.reorth_steps), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,

@@ -158,12 +158,20 @@ __device__ void tri_lu(const double *alpha, const double *beta, int64_t m, doubl
     const int lane = threadIdx.x & 63;
     double a = alpha[0] - lam;
     double b = (m > 1) ? beta[0] : 0.0;
+    // operands of rows j0..j0+63 and j0+1..j0+64, one per lane; the next
+    // chunk's are loaded while a chunk is eliminated
+    double nal1 = (lane + 1 < m) ? alpha[lane + 1] - lam : 0.0;
+    double nbe0 = (lane < m - 1) ? beta[lane] : 0.0;
+    double nbe1 = (lane + 1 < m - 1) ? beta[lane + 1] : 0.0;
     for (int64_t j0 = 0; j0 < m; j0 += 64) {
-        // operands of rows j0..j0+63 and j0+1..j0+64, one per lane
         const int64_t jl = j0 + lane;
-        const double al1 = (jl + 1 < m) ? alpha[jl + 1] - lam : 0.0;
-        const double be0 = (jl < m - 1) ? beta[jl] : 0.0;
-        const double be1 = (jl + 1 < m - 1) ? beta[jl + 1] : 0.0;
+        const double al1 = nal1, be0 = nbe0, be1 = nbe1;
+        {
+            const int64_t jn = jl + 64;
+            nal1 = (jn + 1 < m) ? alpha[jn + 1] - lam : 0.0;
+            nbe0 = (jn < m - 1) ? beta[jn] : 0.0;
+            nbe1 = (jn + 1 < m - 1) ? beta[jn + 1] : 0.0;
+        }
         double r0 = 0.0, r1 = 0.0, r2 = 0.0, rm = 0.0, rp = 0.0;
         const int cnt = (m - j0 < 64) ? (int)(m - j0) : 64;
         for (int t = 0; t < cnt; ++t) {
@@ -200,13 +208,21 @@ __device__ void tri_solve(const double *f, int64_t m, double *x)
 {
     const double *u0 = f, *u1 = f + m, *u2 = f + 2 * m, *ml = f + 3 * m, *pv = f + 4 * m;
     const int lane = threadIdx.x & 63;
-    // forward: y = L^-1 P x
+    // forward: y = L^-1 P x (the next chunk's operands are loaded while a
+    // chunk is processed; they lie beyond the entries this chunk writes)
     double r = x[0];
+    double nmm = (lane < m) ? ml[lane] : 0.0;
+    double npp = (lane < m) ? pv[lane] : 0.0;
+    double nxn = (lane + 1 < m) ? x[lane + 1] : 0.0;
     for (int64_t j0 = 0; j0 < m; j0 += 64) {
         const int64_t jl = j0 + lane;
-        const double mm = (jl < m) ? ml[jl] : 0.0;
-        const double pp = (jl < m) ? pv[jl] : 0.0;
-        const double xn = (jl + 1 < m) ? x[jl + 1] : 0.0;
+        const double mm = nmm, pp = npp, xn = nxn;
+        {
+            const int64_t jn = jl + 64;
+            nmm = (jn < m) ? ml[jn] : 0.0;
+            npp = (jn < m) ? pv[jn] : 0.0;
+            nxn = (jn + 1 < m) ? x[jn + 1] : 0.0;
+        }
         double yout = 0.0;
         const int cnt = (m - j0 < 64) ? (int)(m - j0) : 64;
         for (int t = 0; t < cnt; ++t) {
@@ -225,12 +241,31 @@ __device__ void tri_solve(const double *f, int64_t m, double *x)
     }
     // back: U z = y, from the bottom
     double z1 = 0.0, z2 = 0.0;  // z[j+1], z[j+2]
+    // chunks from the bottom; the one above is loaded while a chunk is solved
+    double na0, na1, na2, nyv;
+    {
+        const int64_t j0 = (m - 64 > 0) ? m - 64 : 0;
+        const int64_t jl = j0 + lane;
+        const bool in = jl < m;
+        na0 = in ? u0[jl] : 1.0;
+        na1 = in ? u1[jl] : 0.0;
+        na2 = in ? u2[jl] : 0.0;
+        nyv = in ? x[jl] : 0.0;
+    }
     for (int64_t j1 = m; j1 > 0; j1 -= 64) {
         const int64_t j0 = (j1 - 64 > 0) ? j1 - 64 : 0;
         const int64_t jl = j0 + lane;
         const bool in = jl < j1;
-        const double a0 = in ? u0[jl] : 1.0, a1 = in ? u1[jl] : 0.0, a2 = in ? u2[jl] : 0.0;
-        const double yv = in ? x[jl] : 0.0;
+        const double a0 = na0, a1 = na1, a2 = na2, yv = nyv;
+        if (j0 > 0) {
+            const int64_t p0 = (j0 - 64 > 0) ? j0 - 64 : 0;
+            const int64_t pl = p0 + lane;
+            const bool pin = pl < j0;
+            na0 = pin ? u0[pl] : 1.0;
+            na1 = pin ? u1[pl] : 0.0;
+            na2 = pin ? u2[pl] : 0.0;
+            nyv = pin ? x[pl] : 0.0;
+        }
         double zout = 0.0;
         for (int t = (int)(j1 - j0) - 1; t >= 0; --t) {
             const double z = (rdlane(yv, t) - rdlane(a1, t) * z1 - rdlane(a2, t) * z2) / rdlane(a0, t);
