@@ -136,6 +136,10 @@ static int64_t eff_max_steps(int64_t n, int64_t s, const gsyeig_opts *o)
 
 static int64_t round_ld(int64_t n) { return cdiv(n, 64) * 64; }
 
+// rows of the outer blocks of the Cholesky factorisation (rank of the
+// deferred trailing updates); a multiple of the 64-row diagonal blocks
+constexpr int64_t POTRF_OUTER = 256;
+
 // ------------------------------------------------------------------ steps
 // Block data of the factor used by the solves, one WS_DINV allocation:
 // [Dinv_i | M_i = Dinv_i U_{i,i+1} | M'_i = Dinv_i^T U_{i-1,i}^T], 64x64 each.
@@ -638,15 +642,33 @@ static int potrf_core(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, double
         pd.C = B + r0 * ldb + c0; pd.ldc = ldb; pd.c_layout = 1;
         pd.alpha = 1.0; pd.beta = 0.0;
         TRY(launch_gemm_f64(pd, ctx->stream));
-        // trailing update of the upper triangle: B_>k,>k -= P^T P
-        GemmDesc sd{};
-        sd.m = m2; sd.n = m2; sd.k = r;
-        sd.A = B + r0 * ldb + c0; sd.lda = ldb; sd.a_layout = 0;    // A(i,k) = P[k][i]
-        sd.B = B + r0 * ldb + c0; sd.ldb = ldb; sd.b_layout = 1;    // B(k,j) = P[k][j]
-        sd.C = B + c0 * ldb + c0; sd.ldc = ldb; sd.c_layout = 1;
-        sd.alpha = -1.0; sd.beta = 1.0;
-        sd.upper_only = 1;
-        TRY(launch_gemm_f64(sd, ctx->stream));
+        // trailing update of the upper triangle, B_>k,>k -= P^T P, in two
+        // levels: the rows of this outer block of POTRF_OUTER rows at once
+        // (the next diagonal blocks need them), the rows below it by one
+        // rank-POTRF_OUTER product when the outer block is done -- the
+        // trailing matrix is then read and written once per POTRF_OUTER
+        // columns instead of once per 64
+        const int64_t K0 = (r0 / POTRF_OUTER) * POTRF_OUTER;
+        const int64_t Kend = std::min<int64_t>(n, K0 + POTRF_OUTER);
+        if (Kend > c0) {
+            GemmDesc sd{};
+            sd.m = Kend - c0; sd.n = m2; sd.k = r;
+            sd.A = B + r0 * ldb + c0; sd.lda = ldb; sd.a_layout = 0;    // A(i,k) = P[k][i]
+            sd.B = B + r0 * ldb + c0; sd.ldb = ldb; sd.b_layout = 1;    // B(k,j) = P[k][j]
+            sd.C = B + c0 * ldb + c0; sd.ldc = ldb; sd.c_layout = 1;
+            sd.alpha = -1.0; sd.beta = 1.0;
+            sd.upper_only = 1;
+            TRY(launch_gemm_f64(sd, ctx->stream));
+        } else if (n > Kend) {
+            GemmDesc bd{};
+            bd.m = n - Kend; bd.n = n - Kend; bd.k = Kend - K0;
+            bd.A = B + K0 * ldb + Kend; bd.lda = ldb; bd.a_layout = 0;
+            bd.B = B + K0 * ldb + Kend; bd.ldb = ldb; bd.b_layout = 1;
+            bd.C = B + Kend * ldb + Kend; bd.ldc = ldb; bd.c_layout = 1;
+            bd.alpha = -1.0; bd.beta = 1.0;
+            bd.upper_only = 1;
+            TRY(launch_gemm_f64(bd, ctx->stream));
+        }
     }
     return 0;
 }
@@ -689,11 +711,22 @@ static int potrf_mixed_enqueue(gsyeig_ctx *ctx, int64_t n, const double *B, int6
         pd.alpha = 1.0; pd.beta = 0.0;
         pd.f32 = 1;
         TRY(launch_gemm(pd, ctx->stream));
+        // two-level trailing update as in potrf_core
+        const int64_t K0 = (r0 / POTRF_OUTER) * POTRF_OUTER;
+        const int64_t Kend = std::min<int64_t>(n, K0 + POTRF_OUTER);
         GemmDesc sd{};
-        sd.m = m2; sd.n = m2; sd.k = r;
-        sd.A = W + r0 * ldw + c0; sd.lda = ldw; sd.a_layout = 0; sd.a_f32 = 1;
-        sd.B = W + r0 * ldw + c0; sd.ldb = ldw; sd.b_layout = 1; sd.b_f32 = 1;
-        sd.C = W + c0 * ldw + c0; sd.ldc = ldw; sd.c_layout = 1; sd.c_f32 = 1;
+        if (Kend > c0) {
+            sd.m = Kend - c0; sd.n = m2; sd.k = r;
+            sd.A = W + r0 * ldw + c0; sd.B = W + r0 * ldw + c0; sd.C = W + c0 * ldw + c0;
+        } else if (n > Kend) {
+            sd.m = n - Kend; sd.n = n - Kend; sd.k = Kend - K0;
+            sd.A = W + K0 * ldw + Kend; sd.B = W + K0 * ldw + Kend; sd.C = W + Kend * ldw + Kend;
+        } else {
+            continue;
+        }
+        sd.lda = ldw; sd.a_layout = 0; sd.a_f32 = 1;
+        sd.ldb = ldw; sd.b_layout = 1; sd.b_f32 = 1;
+        sd.ldc = ldw; sd.c_layout = 1; sd.c_f32 = 1;
         sd.alpha = -1.0; sd.beta = 1.0;
         sd.upper_only = 1;
         sd.f32 = 1;
