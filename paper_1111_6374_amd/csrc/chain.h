@@ -41,6 +41,29 @@ __device__ __forceinline__ double settle(unsigned long long v, const double *p, 
     return settle_slow(v, p, err);
 }
 
+// The same with a longer sleep between polls, for waits off the chain's
+// critical path (values a workgroup needs only several links later): fewer
+// requests on the lines the next link is waiting for.
+__device__ __noinline__ double settle_lazy_slow(unsigned long long v, const double *p, unsigned *err)
+{
+    unsigned it = 0;
+    while (v == STAGE_SENTINEL) {
+        if (++it > SPIN_LIMIT) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0.0;
+        }
+        __builtin_amdgcn_s_sleep(16);
+        v = ld_bits(p);
+    }
+    return __longlong_as_double((long long)v);
+}
+
+__device__ __forceinline__ double settle_lazy(unsigned long long v, const double *p, unsigned *err)
+{
+    if (__builtin_expect(v != STAGE_SENTINEL, 1)) return __longlong_as_double((long long)v);
+    return settle_lazy_slow(v, p, err);
+}
+
 __device__ __forceinline__ double rdlane(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

@@ -241,16 +241,39 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(SkArgs g)
     const int jb = tid / BPC, kb = (tid % BPC) * NBV;
 
     TA ra[NA];
-    TC rb[NBV];
+    double rb[NBV];
     auto fetch = [&](int64_t k0) {
-        const bool full = g.vec && tm0 + SK_TM <= g.m && k0 + TK <= g.k;
+        // B first: its few loads complete before the A slab, which then
+        // stays in flight through the products of the current slab
+        // uniform branch again: a column beyond n is read from column n - 1
+        // (zeroed in stash), so no load is predicated; the values stay raw
+        // until stash, so the loads remain in flight during the products
+        const bool bfull = __builtin_amdgcn_readfirstlane((int)(g.vec && k0 + TK <= g.k));
+        if (bfull) {
+            const double *bsrc = g.B + (int64_t)(jb < g.n ? jb : g.n - 1) * g.ldb + k0 + kb;
 #pragma unroll
-        for (int v = 0; v < NAV; ++v) {
-            int ii, kk;
-            a_pos(v, ii, kk);
-            const int64_t gi = tm0 + ii, gk = k0 + kk;
-            const TA *src = (AL == 1) ? Ap + gi * g.lda + gk : Ap + gk * g.lda + gi;
-            if (full) {
+            for (int u = 0; u < NBV; u += 2) {
+                const double2 q = *(const double2 *)(bsrc + u);
+                rb[u] = q.x;
+                rb[u + 1] = q.y;
+            }
+        } else {
+            const double *bsrc = g.B + (int64_t)jb * g.ldb + k0 + kb;
+#pragma unroll
+            for (int u = 0; u < NBV; ++u)
+                rb[u] = (jb < g.n && k0 + kb + u < g.k) ? bsrc[u] : 0.0;
+        }
+        // one uniform branch around the whole slab, so that the vector loads
+        // of the common (interior, aligned) case form one block and are all
+        // in flight together
+        const bool full = __builtin_amdgcn_readfirstlane((int)(g.vec && tm0 + SK_TM <= g.m && k0 + TK <= g.k));
+        if (full) {
+#pragma unroll
+            for (int v = 0; v < NAV; ++v) {
+                int ii, kk;
+                a_pos(v, ii, kk);
+                const int64_t gi = tm0 + ii, gk = k0 + kk;
+                const TA *src = (AL == 1) ? Ap + gi * g.lda + gk : Ap + gk * g.lda + gi;
                 if constexpr (sizeof(TA) == 4) {
                     const float4 q = *(const float4 *)src;
                     ra[v * 4 + 0] = q.x; ra[v * 4 + 1] = q.y; ra[v * 4 + 2] = q.z; ra[v * 4 + 3] = q.w;
@@ -258,7 +281,13 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(SkArgs g)
                     const double2 q = *(const double2 *)src;
                     ra[v * 2 + 0] = q.x; ra[v * 2 + 1] = q.y;
                 }
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NAV; ++v) {
+                int ii, kk;
+                a_pos(v, ii, kk);
+                const int64_t gi = tm0 + ii, gk = k0 + kk;
 #pragma unroll
                 for (int u = 0; u < VA; ++u) {
                     const int64_t ei = gi + ((AL == 1) ? 0 : u), ek = gk + ((AL == 1) ? u : 0);
@@ -266,20 +295,6 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(SkArgs g)
                                                             : (TA)0;
                 }
             }
-        }
-        const bool bfull = g.vec && k0 + TK <= g.k && jb < g.n;
-        const double *bsrc = g.B + (int64_t)jb * g.ldb + k0 + kb;
-        if (bfull) {
-#pragma unroll
-            for (int u = 0; u < NBV; u += 2) {
-                const double2 q = *(const double2 *)(bsrc + u);
-                rb[u] = (TC)q.x;
-                rb[u + 1] = (TC)q.y;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < NBV; ++u)
-                rb[u] = (jb < g.n && k0 + kb + u < g.k) ? (TC)bsrc[u] : (TC)0;
         }
     };
     auto stash = [&]() {
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(SkArgs g)
             }
         }
 #pragma unroll
-        for (int u = 0; u < NBV; ++u) Bs[kb + u][jb] = rb[u];
+        for (int u = 0; u < NBV; ++u) Bs[kb + u][jb] = (jb < g.n) ? (TC)rb[u] : (TC)0;
     };
 
     V4 acc[2][NBLK];

@@ -172,17 +172,19 @@ __global__ __launch_bounds__(256) void k_gemv_t_parts(const double *__restrict__
         const int64_t i = base + threadIdx.x + 256 * p;
         zr[p] = (i < n) ? z[i] : 0.0;
     }
+    // every load from a clamped in-bounds address, unconditionally (rows
+    // beyond n meet zr = 0; columns beyond kcols are never written out), so
+    // all 64 loads of a thread are in flight together
     double acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         acc[c] = 0.0;
-        if (c0 + c < kcols) {
-            const double *v = V + (c0 + c) * ldv;
+        const int64_t cc = (c0 + c < kcols) ? c0 + c : kcols - 1;
+        const double *v = V + cc * ldv;
 #pragma unroll
-            for (int p = 0; p < RB / 256; ++p) {
-                const int64_t i = base + threadIdx.x + 256 * p;
-                if (i < n) acc[c] = fma(v[i], zr[p], acc[c]);
-            }
+        for (int p = 0; p < RB / 256; ++p) {
+            const int64_t i = base + threadIdx.x + 256 * p;
+            acc[c] = fma(v[i < n ? i : n - 1], zr[p], acc[c]);
         }
     }
     const int w = threadIdx.x >> 6;
@@ -221,18 +223,25 @@ __global__ __launch_bounds__(512) void k_gemv_n_update(const double *__restrict_
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * 64 + lane;
     const bool ok = r < n;
+    // wave w takes a contiguous eighth of the columns, 16 column loads in
+    // flight per lane (8 KB per wave), so the streaming of V is not bound by
+    // the latency of a few outstanding loads
     double acc = 0.0;
     if (ok) {
-        int64_t c = w;
-        for (; c + 24 < kcols; c += 32) {
-            const double v0 = V[c * ldv + r], v1 = V[(c + 8) * ldv + r];
-            const double v2 = V[(c + 16) * ldv + r], v3 = V[(c + 24) * ldv + r];
-            acc = fma(v0, h[c], acc);
-            acc = fma(v1, h[c + 8], acc);
-            acc = fma(v2, h[c + 16], acc);
-            acc = fma(v3, h[c + 24], acc);
+        const int64_t per = (kcols + 7) / 8;
+        const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform: h is read by scalar loads
+        const int64_t cb = wu * per, ce = (cb + per < kcols) ? cb + per : kcols;
+        const double *Vr = V + r;
+        int64_t c = cb;
+        for (; c + 16 <= ce; c += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = Vr[(c + u) * ldv];
+            __builtin_amdgcn_sched_barrier(0);  // all 16 loads issued before the first use
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = fma(v[u], h[c + u], acc);
         }
-        for (; c < kcols; c += 8) acc = fma(V[c * ldv + r], h[c], acc);
+        for (; c < ce; ++c) acc = fma(Vr[c * ldv], h[c], acc);
     }
     s[w][lane] = acc;
     __syncthreads();

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
             const int p = l & (4 * GRP - 1);
             const int64_t prow = rowof(t0 + (p >> 2)) + (p & 3);
             const unsigned long long pv = ld_bits(stage + prow);
-            const double zmine = settle(pv, stage + prow, &ctl->err);
+            const double zmine = settle_lazy(pv, stage + prow, &ctl->err);
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
                 const bool live = (t0 + g < ntile);
