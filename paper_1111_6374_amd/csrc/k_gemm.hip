@@ -85,15 +85,28 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
     __shared__ TC As[TK][TM + PAD];
     __shared__ TC Bs[TK][TN + PAD];
 
-    TC ra[4], rb[4];
+    // The next slab is fetched while the current one is multiplied: loads
+    // come from clamped in-bounds indices (no predicated load) and stay in
+    // their storage type until stash, which converts them and zeroes the
+    // out-of-range ones -- nothing waits for the loads before the products.
+    TA ra[4];
+    TB rb[4];
+    unsigned am = 0, bm = 0;
     auto fetch = [&](int64_t k0) {
+        am = bm = 0;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             int ii, kk;
             if constexpr (AL == 0) { ii = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
             const int64_t gi = tm0 + ii, gk = k0 + kk;
-            ra[p] = (gi < g.m && gk < kend) ? (TC)load_op<TA, AL>(Ap, g.lda, gi, gk, g.a_diag) : (TC)0;
+            const bool ok = gi < g.m && gk < kend;
+            am |= (unsigned)ok << p;
+            if constexpr (AL == 2) {
+                ra[p] = ok ? load_op<TA, AL>(Ap, g.lda, gi, gk, g.a_diag) : (TA)0;
+            } else {
+                ra[p] = load_op<TA, AL>(Ap, g.lda, gi < g.m ? gi : g.m - 1, gk < kend ? gk : kend - 1, nullptr);
+            }
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -101,7 +114,8 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
             if constexpr (BL == 1) { jj = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
             const int64_t gk = k0 + kk, gj = tn0 + jj;
-            rb[p] = (gk < kend && gj < g.n) ? (TC)load_op<TB, BL>(Bp, g.ldb, gk, gj, nullptr) : (TC)0;
+            bm |= (unsigned)(gk < kend && gj < g.n) << p;
+            rb[p] = load_op<TB, BL>(Bp, g.ldb, gk < kend ? gk : kend - 1, gj < g.n ? gj : g.n - 1, nullptr);
         }
     };
     auto stash = [&]() {
@@ -110,14 +124,14 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
             int ii, kk;
             if constexpr (AL == 0) { ii = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
-            As[kk][ii] = ra[p];
+            As[kk][ii] = ((am >> p) & 1u) ? (TC)ra[p] : (TC)0;
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             int kk, jj;
             if constexpr (BL == 1) { jj = tid & 63; kk = (tid >> 6) + 4 * p; }
             else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
-            Bs[kk][jj] = rb[p];
+            Bs[kk][jj] = ((bm >> p) & 1u) ? (TC)rb[p] : (TC)0;
         }
     };
 
