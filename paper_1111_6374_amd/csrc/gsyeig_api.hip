@@ -1068,8 +1068,9 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
         if (blz_check_dims(n, s, nv, &o)) return -8;
         b += blz_bytes(n, s, nv, &o);                                 // block basis, projected matrix
     }
-    if (o.reorth == 2)  // omega estimates, Cholesky QR of the Ritz vectors
-        b += sizeof(double) * (size_t)(3 * (mmax + 8) + 8 + n * s);
+    if (o.reorth == 2)  // omega estimates; Gram matrix of the basis and its diagonal-block inverses
+        b += sizeof(double) * ((size_t)(3 * (mmax + 8) + 8) + (size_t)mmax * (size_t)mmax +
+                               (size_t)cdiv(mmax, NB) * NB * NB);
     if (o.invert) {
         b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
         if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
