@@ -293,15 +293,26 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     else
         TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
-    if (op.f32)
-        TRY(launch_symv_f32(ctx, n, op.A32, op.lda32, tmp, z));
-    else
+    if (op.f32 || ctx->trsv_block != 64) {
+        // KI2's tile pass, then KI3 on U = D (I + W) summing the partials of
+        // its own rows (no separate reduction launch)
+        double *Pr, *Pc;
+        int maxch, ch;
+        if (op.f32)
+            TRY(launch_symv_partials_f32(ctx, n, op.A32, op.lda32, tmp, &Pr, &Pc, &maxch, &ch));
+        else
+            TRY(launch_symv_partials(ctx, n, op.A, op.lda, tmp, &Pr, &Pc, &maxch, &ch));
+        if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
+        if (op.f32)
+            TRY(launch_trsv_w_t_rows_f32(op.W32, op.ldw32, n, op.sb, Pr, Pc, maxch, ch, z, ctx->ctl_t, ctx->stream));
+        else
+            TRY(launch_trsv_w_t_rows((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB],
+                                     Pr, Pc, maxch, ch, z, ctx->ctl_t, ctx->stream));
+    } else {
         TRY(launch_symv(ctx, n, op.A, op.lda, tmp, z));
-    if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
-    if (op.f32)
-        TRY(launch_trsv_w_t_f32(op.W32, op.ldw32, n, op.sb, z, z, ctx->ctl_t, ctx->stream));
-    else
+        if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
         TRY(solve_t(ctx, n, op.U, op.ldu, op.Dinv, z, z));
+    }
     if (sample) {
         HIP_TRY(hipEventRecord(e[3], ctx->stream));
         ctx->npev += 4;

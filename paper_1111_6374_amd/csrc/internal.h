@@ -179,6 +179,16 @@ int launch_backsolve_f32(const float *U, int64_t ldu, int64_t n, int64_t s, cons
 int launch_upper_to_f32(const double *B, int64_t ldb, float *W, int64_t ldw, int64_t n, hipStream_t st);
 int launch_symv_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x,
                     double *y);
+// KI2's tile pass alone (partials Pr / Pc, maxch slots of ch tiles per block
+// row) and KI3 taking those partials as its right-hand side
+int launch_symv_partials(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double **Pr,
+                         double **Pc, int *maxch, int *ch);
+int launch_symv_partials_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double **Pr,
+                             double **Pc, int *maxch, int *ch);
+int launch_trsv_w_t_rows(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *Pr,
+                         const double *Pc, int maxch, int ch, double *x, PCtl *ctl, hipStream_t st);
+int launch_trsv_w_t_rows_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *Pr,
+                             const double *Pc, int maxch, int ch, double *x, PCtl *ctl, hipStream_t st);
 int launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
                   hipStream_t st);
 // M holds [M_i | M'_i] for all blocks (see launch_make_m)

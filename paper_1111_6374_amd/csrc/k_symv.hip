@@ -419,8 +419,11 @@ __global__ __launch_bounds__(256) void k_symv_reduce(const double *__restrict__ 
 
 }  // namespace
 
+// The tile pass of y = A x: partials into Pr / Pc (maxch chunk slots of
+// SYMV_CH tiles per block row), summed by k_symv_reduce or by the KI3 sweep.
 template <typename T>
-static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, const double *x, double *y)
+static int symv_tiles_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, const double *x, double **Pr_out,
+                        double **Pc_out, int *maxch_out)
 {
     const int nblk = (int)cdiv(n, NB);
     // FP32 storage with 16-byte rows of 4: the quad-load kernel (measured
@@ -465,8 +468,21 @@ static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, co
         hipLaunchKernelGGL(k_symv_tiles_f32<false>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x,
                            items, (double *)pr, (double *)pc);
     if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    *Pr_out = (double *)pr;
+    *Pc_out = (double *)pc;
+    *maxch_out = maxch;
+    return 0;
+}
+
+template <typename T>
+static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, const double *x, double *y)
+{
+    double *pr, *pc;
+    int maxch, rc;
+    if ((rc = symv_tiles_t<T>(ctx, n, A, lda, x, &pr, &pc, &maxch))) return rc;
+    const int nblk = (int)cdiv(n, NB);
     hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
-                       (const double *)pc, nblk, maxch, n, y, ch);
+                       (const double *)pc, nblk, maxch, n, y, SYMV_CH);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
@@ -513,6 +529,20 @@ int launch_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const 
 int launch_symv_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double *y)
 {
     return launch_symv_t<float>(ctx, n, A, lda, x, y);
+}
+
+int launch_symv_partials(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x, double **Pr,
+                         double **Pc, int *maxch, int *ch)
+{
+    *ch = SYMV_CH;
+    return symv_tiles_t<double>(ctx, n, A, lda, x, Pr, Pc, maxch);
+}
+
+int launch_symv_partials_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double **Pr,
+                             double **Pc, int *maxch, int *ch)
+{
+    *ch = SYMV_CH;
+    return symv_tiles_t<float>(ctx, n, A, lda, x, Pr, Pc, maxch);
 }
 
 // Queue and partials of the KI2 + KI3 fusion: tiles (I, J >= I), block rows

@@ -321,11 +321,20 @@ __device__ __forceinline__ void ki3_symv_round(const FuseT &ft, int64_t n, int n
     __syncthreads();
 }
 
+// KI3's right-hand side given as the SYMV tile partials instead of b
+// (Pr == nullptr: b is used): the workgroup of block row K sums the row parts
+// of K and the column parts of tiles (I, K), I < K, in the order of
+// k_symv_reduce (bitwise the same b), before its far loop -- one launch less.
+struct RowSums {
+    const double *Pr, *Pc;
+    int maxch, ch;
+};
+
 template <typename T, bool SYMV>
 __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int64_t ldw, int64_t n, int nblk,
                                                    const double *__restrict__ UinvT,
                                                    const double *__restrict__ WLt, const double *b, double *x,
-                                                   PCtl *ctl, FuseT ft)
+                                                   PCtl *ctl, FuseT ft, RowSums rs)
 {
     __shared__ int s_blk, s_last;
     __shared__ double s_part[16][NB];
@@ -350,6 +359,29 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
     const bool has_prev = S > 0;
     const int al = loc * NB + 4 * w;  // local index (in S) of this wave's first output
 
+    __shared__ double s_rs[4][NB];
+    if (rs.Pr) {  // uniform
+        if (w < 4) {
+            const int K = i, q = w;
+            const int nch = (nblk - K + rs.ch - 1) / rs.ch;
+            // unrolled so that several loads are in flight; the sums keep
+            // k_symv_reduce's order
+            double sm = 0.0;
+#pragma unroll 8
+            for (int c = q; c < nch; c += 4) sm += rs.Pr[((int64_t)K * rs.maxch + c) * NB + l];
+            const double *pc = rs.Pc + (int64_t)K * nblk * NB + l;
+            int I = q;
+#pragma unroll 4
+            for (; I + 12 < K; I += 16) {
+                const double a0 = pc[(int64_t)I * NB], a1 = pc[(int64_t)(I + 4) * NB];
+                const double a2 = pc[(int64_t)(I + 8) * NB], a3 = pc[(int64_t)(I + 12) * NB];
+                sm += (a0 + a1) + (a2 + a3);
+            }
+#pragma unroll 4
+            for (; I < K; I += 4) sm += pc[(int64_t)I * NB];
+            s_rs[q][l] = sm;
+        }
+    }
     // far tiles: rows of super-blocks T <= S-2, i.e. tiles j < (S-1)*TPS
     double acc = 0.0;
     const int ntile = (S - 1) * TPS;
@@ -466,7 +498,8 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
 #pragma unroll
             for (int q = 0; q < 16; ++q) be += s_b[q][4 * w + l];
         } else {
-            be = (e < n) ? b[e] : 0.0;
+            const int r = 4 * w + l;
+            be = (e >= n) ? 0.0 : rs.Pr ? (s_rs[0][r] + s_rs[1][r]) + (s_rs[2][r] + s_rs[3][r]) : b[e];
         }
         if (e < n) st_bits(stage + e, (unsigned long long)__double_as_longlong(be - ye));
     }
@@ -683,12 +716,12 @@ static int trsv_w_n_t(const T *W, int64_t ldw, int64_t n, const double *sbw, con
 
 template <typename T>
 static int trsv_w_t_t(const T *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x, PCtl *ctl,
-                      hipStream_t st)
+                      hipStream_t st, RowSums rs = RowSums{})
 {
     const int nblk = (int)cdiv(n, NB);
     const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
     hipLaunchKernelGGL((k_trsv_w_t<T, false>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw + nsb * blk,
-                       sbw + 2 * nsb * blk, b, x, ctl, FuseT{});
+                       sbw + 2 * nsb * blk, b, x, ctl, FuseT{}, rs);
     return ok();
 }
 
@@ -757,8 +790,9 @@ int launch_trsv_w_t_symv(const double *W, int64_t ldw, int64_t n, const double *
     const double *UinvT = sbw + nsb * blk, *WLt = sbw + 2 * nsb * blk;
     const double *bnull = nullptr;
     FuseT ft{A, lda, items, ntiles, Pr, Pc, xin};
+    RowSums rs{};
     void *args[] = {(void *)&W,     (void *)&ldw,   (void *)&n, (void *)&nblk, (void *)&UinvT, (void *)&WLt,
-                    (void *)&bnull, (void *)&x,     (void *)&ctl, (void *)&ft};
+                    (void *)&bnull, (void *)&x,     (void *)&ctl, (void *)&ft, (void *)&rs};
     if (hipLaunchCooperativeKernel((const void *)k_trsv_w_t<double, true>, dim3(nblk), dim3(1024), args, 0, st) !=
         hipSuccess)
         return GSYEIG_EHIP;
@@ -784,6 +818,20 @@ int launch_trsv_w_t_f32(const float *W, int64_t ldw, int64_t n, const double *sb
                         PCtl *ctl, hipStream_t st)
 {
     return trsv_w_t_t<float>(W, ldw, n, sbw, b, x, ctl, st);
+}
+
+// KI3 with the right-hand side as SYMV tile partials (KI2's reduction done
+// by the sweep's own workgroups)
+int launch_trsv_w_t_rows(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *Pr,
+                         const double *Pc, int maxch, int ch, double *x, PCtl *ctl, hipStream_t st)
+{
+    return trsv_w_t_t<double>(W, ldw, n, sbw, nullptr, x, ctl, st, RowSums{Pr, Pc, maxch, ch});
+}
+
+int launch_trsv_w_t_rows_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *Pr,
+                             const double *Pc, int maxch, int ch, double *x, PCtl *ctl, hipStream_t st)
+{
+    return trsv_w_t_t<float>(W, ldw, n, sbw, nullptr, x, ctl, st, RowSums{Pr, Pc, maxch, ch});
 }
 
 // FP32 copy of an FP64 matrix (rows x cols, leading dimensions lds / ldd)
