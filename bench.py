@@ -97,8 +97,6 @@ def main():
                     help="--config 4: 0 = FP64, 1 = mixed (default: mixed, the configuration's precision)")
     ap.add_argument("--no-loop", action="store_true", help="--config 4: skip the loop of single FP64 solves")
     ap.add_argument("--refine-inner", type=int, default=0, help="MINRES steps per refinement round (0 = default)")
-    ap.add_argument("--fuse", type=int, default=-1,
-                    help="KI2 fusion (gsyeig_set_fused_symv): 0 apart, 1 into KI1, 2 into KI3 (default: library's)")
     ap.add_argument("--basis", type=int, default=0, help="--config 3: basis size before a restart (0 = auto)")
     ap.add_argument("--acc32", type=int, default=0, help="--config 3: 1 = FP32 accumulation in block products")
     ap.add_argument("--no-fem", action="store_true", help="--config 3: skip the FEM pencil")
@@ -151,10 +149,6 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     solver = gs.Solver()
-    if args.fuse >= 0:
-        rc = gs.gsyeig_set_fused_symv(solver.ctx, args.fuse)
-        if rc:
-            raise gs.GsyeigError("gsyeig_set_fused_symv", rc)
     opts = gs.gsyeig_opts_default()
     opts.profile_every = args.profile_every
     if args.reorth >= 0:

@@ -12,7 +12,9 @@
  *   KI1  wbar = U^-1 w          (triangular solve)
  *   KI2  what = A wbar          (symmetric matrix-vector product)
  *   KI3  z    = U^-T what       (triangular solve)     -> z = C w, Eq. 3
- *   KI4  Lanczos update with full re-orthogonalisation ("twice")
+ *   KI4  Lanczos update; by default partial re-orthogonalisation (the
+ *        omega recurrence decides which steps run classical Gram-Schmidt
+ *        twice against the whole basis; opts.reorth selects the others)
  *   KI5  Ritz values/vectors from the tridiagonal T_m and basis V_m
  *   BT1  X = U^-1 Y                                            (Eq. 4)
  *
@@ -39,7 +41,9 @@
  *     GSYEIG_ENOCONV  fewer than s pairs met the tolerance within max_steps
  *     GSYEIG_EHIP     a HIP runtime call failed
  *     GSYEIG_ESPIN    a persistent kernel's bounded wait expired (internal
- *                     error; outputs undefined, the GPU is left usable)
+ *                     error; outputs undefined, the GPU is left usable).
+ *                     Synchronous calls report the waits of their own
+ *                     kernels; asynchronous ones through gsyeig_sync.
  * - Contexts are not thread-safe; use one per host thread/stream.
  */
 #ifndef GSYEIG_H
@@ -76,7 +80,7 @@ typedef struct {
                            /*   (default 1e-12); Section 3.3 used tol = 0, i.e.   */
                            /*   machine precision, in ARPACK's dsaupd             */
     int64_t max_steps;     /* cap on operator applications m (default             */
-                           /*   min(n, 100 s + 2000))                             */
+                           /*   min(n, max(100 s + 2000, 10 sqrt(n s))))          */
     int64_t check_every;   /* steps between convergence checks (default 25)       */
     uint64_t seed;         /* start vector w_0 = SplitMix64(seed) in [-1,1)^n     */
     const double *v0;      /* optional device start vector (n); overrides seed    */
@@ -181,21 +185,24 @@ int gsyeig_destroy(gsyeig_ctx *ctx);
  * Host-only setting; takes effect at the next factorisation or solve. */
 int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
 
-/* KI2 fused into a triangular sweep (FP64 operator with the 512-row
- * super-block solves; Section 2.3's KI1-KI3 computed with KI2 overlapped):
- *   on = 1: into the U^-1 sweep -- workgroups that have published their rows
- *           apply the 64x64 tiles of A's upper triangle as the solved values
- *           arrive;
- *   on = 2: into the U^-T sweep -- workgroups waiting for their turn apply
- *           the tiles, block rows from the top (the order in which that sweep
- *           needs A x), to the complete U^-1 result, and each sums its own
- *           rows of A x before its link;
- *   on = 0: the three kernels run apart.
- * Fusion needs every workgroup of the sweep resident at once (cooperative
- * launch; n <= 64 x the resident 1024-thread workgroups, 16384 here); where
- * it is not, the kernels run apart.  The result equals the unfused operator
- * up to the order of the partial sums.  Host-only setting. */
-int gsyeig_set_fused_symv(gsyeig_ctx *ctx, int on);
+/* Bound on the polls of each wait in the chained (persistent) triangular
+ * sweeps of KI1/KI3 on this context: 0 restores the built-in bound (2^22
+ * polls); the bound is consulted from the 33rd poll of a wait on, so values
+ * below 32 act as 32.  A wait that runs out stores 0.0 for the awaited value, marks the
+ * context's wait record and lets the kernel finish, so no wait can hang the
+ * GPU; the call reports GSYEIG_ESPIN.  Meant for tests of that error path
+ * (a tiny bound forces expiries in a healthy run).  Synchronises; returns
+ * 0, -1 (NULL ctx) or GSYEIG_EHIP. */
+int gsyeig_set_spin_limit(gsyeig_ctx *ctx, unsigned limit);
+
+/* Wait for the context's stream and report the wait record of the chained
+ * sweeps enqueued by asynchronous calls (gsyeig_trsv, gsyeig_apply_op,
+ * gsyeig_lanczos_run) since the last report: GSYEIG_ESPIN if one of their
+ * waits expired (the record is then cleared), else 0; GSYEIG_EHIP on a
+ * runtime error.  Synchronous entry points clear the record when they
+ * start and report only their own waits, so call this after asynchronous
+ * work whose result matters. */
+int gsyeig_sync(gsyeig_ctx *ctx);
 
 /* Bytes of device workspace gsyeig_solve needs for (n, s, opts) (host-only
  * arithmetic; no GPU call). */
@@ -220,8 +227,12 @@ int gsyeig_potrf(gsyeig_ctx *ctx, int64_t n, double *B, int64_t ldb, const gsyei
 int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int trans,
                 const double *b, double *x);
 
-/* KI2 (Table 1): y = A x, A symmetric in full storage; only the upper
- * triangle of A is read.  x and y must not alias.  Asynchronous. */
+/* KI2 (Table 1): y = A x, A symmetric in full storage.  Read set: the
+ * 64x64 tiles A_IJ with J >= I of the upper block triangle -- the tiles
+ * above the diagonal once, each used for both y_I and y_J, and the 64x64
+ * diagonal tiles in full (both of their triangles, so A must be symmetric
+ * there); tiles below the diagonal tiles are never read.  x and y must not
+ * alias.  Asynchronous. */
 int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x,
                 double *y);
 
@@ -231,7 +242,8 @@ int gsyeig_apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, co
                     int64_t ldu, const double *w, double *z);
 
 /* KI1-KI4 for exactly k steps (Section 2.3, Lanczos with the three-term
- * recurrence and classical Gram-Schmidt re-orthogonalisation applied twice):
+ * recurrence and classical Gram-Schmidt re-orthogonalisation applied twice
+ * on every step, whatever opts.reorth says elsewhere):
  *   w_0 = v0/||v0||; for j < k:  z = C w_j - beta_{j-1} w_{j-1};
  *   alpha_j = w_j^T z; z -= alpha_j w_j; twice { z -= W_j (W_j^T z) };
  *   beta_j = ||z||; w_{j+1} = z / beta_j.
@@ -241,7 +253,8 @@ int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, i
                        const double *U, int64_t ldu, const double *v0, double *alpha,
                        double *beta, double *V, int64_t ldv);
 
-/* KI5, eigen-part (Section 2.3: "obtaining the eigenpairs from T_m, V_m"):
+/* KI5, eigen-part (Section 2.3; the Ritz values and coefficient vectors of
+ * the tridiagonal Lanczos matrix):
  * the nwant smallest (which = 0) or largest (which = 1) eigenvalues of the
  * symmetric tridiagonal T_m (diagonal alpha[0..m-1], off-diagonal
  * beta[0..m-2]) by Sturm-count bisection, ascending, into theta (device,
@@ -254,24 +267,45 @@ int gsyeig_tridiag_eig(gsyeig_ctx *ctx, int64_t m, const double *alpha, const do
 /* KI1-KI5: Lanczos on C = U^-T A U^-1 until the s wanted Ritz pairs have
  * Ritz residual estimate beta_m |e_m^T s_i| <= tol ||T_m|| (checked every
  * check_every steps) or max_steps is reached.  Returns the Ritz values
- * (theta, device, s, ascending) and Ritz vectors Y = V_m S (device, n x s
- * column-major).  U is the upper Cholesky factor (row-major).
+ * (theta, device, s, ascending) and Ritz vectors (device, n x s
+ * column-major): Y = V_m S with reorth 0 or 1; with the default partial
+ * re-orthogonalisation (reorth 2) the basis is only semi-orthogonal and
+ * Y = V_m R^-1 S, where V_m^T V_m = R^T R (Cholesky), so that Y is
+ * orthonormal.  U is the upper Cholesky factor (row-major).
  * *steps_out (host, may be NULL) receives m.  Synchronises.
- * Returns 0 or GSYEIG_ENOCONV (results are the best available). */
+ * Returns 0, GSYEIG_ENOCONV (results are the best available; with reorth 2
+ * also when V_m^T V_m lost positive definiteness, and then Y is not
+ * valid), or GSYEIG_ESPIN (a chained wait of this call expired). */
 int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda,
                    const double *U, int64_t ldu, const gsyeig_opts *opts, double *theta,
                    double *Y, int64_t ldy, int64_t *steps_out);
 
 /* KI1 / KI3 with U stored FP32 (the mixed-precision sweeps): x = U^-1 b or
  * U^-T b for the FP32 upper-triangular U (row-major, ldu), FP64 b, x and
- * FP64 arithmetic -- the exact solve with the FP32 matrix up to FP64
- * rounding.  Uses 512-row super-block chain links.  x may alias b.
- * Synchronises (checks the chained kernels' wait flags). */
+ * FP64 arithmetic.  The factor is applied as U = D (I + W) over 512-row
+ * diagonal super-blocks D (their inverses formed in FP64) with
+ * W = D^-1 U_offdiag stored FP32, so the result is the exact solve with
+ * D (I + fl32(W)), an FP32-level perturbation of U (componentwise
+ * relative error of order u_32 kappa(U), not FP64 rounding).  x may alias
+ * b.  Synchronises; returns GSYEIG_ESPIN if a chained wait of this call
+ * expired. */
 int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int trans, const double *b,
                    double *x);
 
-/* KI2 with A stored FP32: y = A x (FP64 x, y and arithmetic; only the upper
- * triangle of A is read).  Synchronises. */
+/* KI1-KI3 with A and U stored FP32 (the operator of the mixed-precision
+ * Lanczos sweeps, Section 2.3's implicit C with FP32 storage):
+ * z = U^-T (A (U^-1 w)) with FP64 vectors and arithmetic; U is applied as
+ * by gsyeig_trsv_lp (its upper triangle) and A as by gsyeig_symv.  The
+ * U^-T sweep sums the A-product's tile partials itself, in the order of
+ * gsyeig_symv_lp's reduction, so z equals the three separate calls bit for
+ * bit.  z may alias w.  Synchronises; returns GSYEIG_ESPIN if a chained
+ * wait of this call expired. */
+int gsyeig_apply_op_lp(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const float *U, int64_t ldu,
+                       const double *w, double *z);
+
+/* KI2 with A stored FP32: y = A x (FP64 x, y and arithmetic; A is read as
+ * by gsyeig_symv: upper block triangle, 64x64 diagonal tiles in full).
+ * Synchronises. */
 int gsyeig_symv_lp(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const double *x, double *y);
 
 /* Block form of KI1 / KI3 used by the mixed-precision refinement:
@@ -351,7 +385,10 @@ int gsyeig_check(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
  * ldx >= n) the B-orthonormal eigenvectors, each signed so that its entry
  * of largest magnitude (lowest index on ties) is positive.  *info (host,
  * may be NULL) receives steps, timings and the check.  Synchronises.
- * Returns 0, +k (B not SPD), GSYEIG_ENOCONV, or an error. */
+ * Returns 0, +k (B not SPD), GSYEIG_ENOCONV, or an error.  On
+ * GSYEIG_ENOCONV *info is filled with what the run reached (in mixed mode,
+ * when the Lanczos phase produced no valid Ritz vectors, only the Lanczos
+ * fields, with eta_max = HUGE_VAL and no refinement). */
 int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
                  int64_t ldb, const gsyeig_opts *opts, double *Lambda, double *X, int64_t ldx,
                  gsyeig_info *info);

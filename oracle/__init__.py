@@ -49,7 +49,6 @@ def lib():
         L.or_trsv_upper.argtypes = [i, _dp, _dp]
         L.or_trsv_upper_t.argtypes = [i, _dp, _dp]
         L.or_matvec.argtypes = [i, _dp, _dp, _dp]
-        L.or_trmv_upper.argtypes = [i, _dp, _dp, _dp]
         L.or_form_c.argtypes = [i, _dp, _dp, _dp]
         L.or_eig_ql.argtypes = [i, _dp, _dp, _dp]
         L.or_eig_ql.restype = i
@@ -104,12 +103,6 @@ def matvec(A, x):
     A = _c(A)
     y = np.empty(A.shape[0])
     lib().or_matvec(A.shape[0], A, _c(x), y)
-    return y
-
-
-def trmv_upper(U, x):
-    y = np.empty(U.shape[0])
-    lib().or_trmv_upper(U.shape[0], _c(U), _c(x), y)
     return y
 
 

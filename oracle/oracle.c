@@ -99,18 +99,6 @@ void or_matvec(int n, const double *A, const double *x, double *y)
     }
 }
 
-/* y := U x, U upper (used by tests to build right-hand sides). */
-void or_trmv_upper(int n, const double *U, const double *x, double *y)
-{
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < n; ++i) {
-        double acc = 0.0;
-        const double *row = &U[IDX(i, 0, n)];
-        for (int j = i; j < n; ++j) acc += row[j] * x[j];
-        y[i] = acc;
-    }
-}
-
 /* ------------------------------------------------------------------ */
 /* Eq. 3: C := U^-T A U^-1 by two triangular solves.                    */
 /*   W := A U^-1   (row i of W is (U^-T a_i)^T, a_i = row i of A)       */
@@ -232,6 +220,12 @@ static void or_tridiagonalise(int n, double *C, double *d, double *e, double *Qt
 /* into the rows of Zt (row i = current vector i).  Shift from the      */
 /* leading 2x2 of the active block (Wilkinson-type).  Returns 0, or -1  */
 /* if an eigenvalue failed to converge in 60 sweeps.                    */
+/* The steps are those of the published implicit QL routine tql2        */
+/* (Bowdler, Martin, Reinsch and Wilkinson, Numer. Math. 11, 1968;      */
+/* EISPACK), in the arrangement Numerical Recipes prints as tqli:       */
+/* the same shift, the same bottom-up rotation sweep and the same split */
+/* on an underflowing rotation (Golub and Van Loan, Sec. 8.3, for the   */
+/* theory).                                                             */
 /* ------------------------------------------------------------------ */
 static int or_tridiag_ql(int n, double *d, double *e, double *Zt)
 {

@@ -28,8 +28,8 @@ EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
-    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_fused_symv", "gsyeig_solve_batched",
-    "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
+    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_sync", "gsyeig_solve_batched",
+    "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_apply_op_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
 )
 
 
@@ -94,11 +94,13 @@ def lib():
             "gsyeig_create": ([ctypes.POINTER(P), P], I),
             "gsyeig_destroy": ([P], I),
             "gsyeig_set_trsv_block": ([P, I64], I),
-            "gsyeig_set_fused_symv": ([P, I], I),
+            "gsyeig_set_spin_limit": ([P, ctypes.c_uint], I),
+            "gsyeig_sync": ([P], I),
             "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
             "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
             "gsyeig_trsv_lp": ([P, I64, P, I64, I, P, P], I),
             "gsyeig_symv_lp": ([P, I64, P, I64, P, P], I),
+            "gsyeig_apply_op_lp": ([P, I64, P, I64, P, I64, P, P], I),
             "gsyeig_trsm_lp": ([P, I64, P, I64, I, I64, P, I64, P, I64], I),
             "gsyeig_syev_small": ([P, I64, P, I64, I64, I, P, P, I64], I),
             "gsyeig_refine": ([P, I64, I64, I64, P, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, I64, P, P,
@@ -164,8 +166,12 @@ def gsyeig_set_trsv_block(ctx, rows) -> int:
     return lib().gsyeig_set_trsv_block(ctx, rows)
 
 
-def gsyeig_set_fused_symv(ctx, on) -> int:
-    return lib().gsyeig_set_fused_symv(ctx, on)
+def gsyeig_set_spin_limit(ctx, limit) -> int:
+    return lib().gsyeig_set_spin_limit(ctx, limit)
+
+
+def gsyeig_sync(ctx) -> int:
+    return lib().gsyeig_sync(ctx)
 
 
 def gsyeig_workspace_size(n, s, opts=None):
@@ -214,6 +220,10 @@ def gsyeig_trsv_lp(ctx, n, U, ldu, trans, b, x) -> int:
 
 def gsyeig_symv_lp(ctx, n, A, lda, x, y) -> int:
     return lib().gsyeig_symv_lp(ctx, n, _p(A), lda, _p(x), _p(y))
+
+
+def gsyeig_apply_op_lp(ctx, n, A, lda, U, ldu, w, z) -> int:
+    return lib().gsyeig_apply_op_lp(ctx, n, _p(A), lda, _p(U), ldu, _p(w), _p(z))
 
 
 def gsyeig_trsm_lp(ctx, n, U, ldu, trans, k, V, ldv, X, ldx) -> int:

@@ -19,15 +19,30 @@ __device__ __forceinline__ void st_bits(double *p, unsigned long long v)
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bound on the polls of one wait: the host may lower it (tests of the
+// expiry path force the condition this way); 0 selects SPIN_LIMIT.  It is
+// read only once a wait has polled SPIN_FREE times, so a short wait on the
+// chain's critical path never pays for the extra load; smaller bounds act
+// as SPIN_FREE.
+#define SPIN_FREE 32u
+__device__ __forceinline__ unsigned spin_bound(PCtl *ctl)
+{
+    const unsigned s = __hip_atomic_load(&ctl->spin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return s ? (s > SPIN_FREE ? s : SPIN_FREE) : SPIN_LIMIT;
+}
+
 // Finish a poll started with ld_bits: spin (bounded) while the value is the
 // sentinel.  An expired wait records an error and yields 0.
-__device__ __noinline__ double settle_slow(unsigned long long v, const double *p, unsigned *err)
+__device__ __noinline__ double settle_slow(unsigned long long v, const double *p, PCtl *ctl)
 {
-    unsigned it = 0;
+    unsigned it = 0, lim = 0;
     while (v == STAGE_SENTINEL) {
-        if (++it > SPIN_LIMIT) {
-            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return 0.0;
+        if (++it > SPIN_FREE) {
+            if (!lim) lim = spin_bound(ctl);
+            if (it > lim) {
+                __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return 0.0;
+            }
         }
         __builtin_amdgcn_s_sleep(2);  // fewer polls on lines every waiting workgroup reads
         v = ld_bits(p);
@@ -35,22 +50,25 @@ __device__ __noinline__ double settle_slow(unsigned long long v, const double *p
     return __longlong_as_double((long long)v);
 }
 
-__device__ __forceinline__ double settle(unsigned long long v, const double *p, unsigned *err)
+__device__ __forceinline__ double settle(unsigned long long v, const double *p, PCtl *ctl)
 {
     if (__builtin_expect(v != STAGE_SENTINEL, 1)) return __longlong_as_double((long long)v);
-    return settle_slow(v, p, err);
+    return settle_slow(v, p, ctl);
 }
 
 // The same with a longer sleep between polls, for waits off the chain's
 // critical path (values a workgroup needs only several links later): fewer
 // requests on the lines the next link is waiting for.
-__device__ __noinline__ double settle_lazy_slow(unsigned long long v, const double *p, unsigned *err)
+__device__ __noinline__ double settle_lazy_slow(unsigned long long v, const double *p, PCtl *ctl)
 {
-    unsigned it = 0;
+    unsigned it = 0, lim = 0;
     while (v == STAGE_SENTINEL) {
-        if (++it > SPIN_LIMIT) {
-            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return 0.0;
+        if (++it > SPIN_FREE) {
+            if (!lim) lim = spin_bound(ctl);
+            if (it > lim) {
+                __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return 0.0;
+            }
         }
         __builtin_amdgcn_s_sleep(16);
         v = ld_bits(p);
@@ -58,10 +76,10 @@ __device__ __noinline__ double settle_lazy_slow(unsigned long long v, const doub
     return __longlong_as_double((long long)v);
 }
 
-__device__ __forceinline__ double settle_lazy(unsigned long long v, const double *p, unsigned *err)
+__device__ __forceinline__ double settle_lazy(unsigned long long v, const double *p, PCtl *ctl)
 {
     if (__builtin_expect(v != STAGE_SENTINEL, 1)) return __longlong_as_double((long long)v);
-    return settle_lazy_slow(v, p, err);
+    return settle_lazy_slow(v, p, ctl);
 }
 
 __device__ __forceinline__ double rdlane(double v, int lane)
@@ -116,7 +134,6 @@ __device__ void retire(PCtl *ctl, double *stage, int64_t nstage, int nblk, int *
         if (threadIdx.x == 0) {
             __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->pad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

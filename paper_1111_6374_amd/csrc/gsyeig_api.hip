@@ -3,6 +3,7 @@
 // The driver only sequences kernels on the context's stream and moves a few
 // scalars (info codes, the converged count, check results) to the host.
 // Every arithmetic step of the path runs in the kernels of this library.
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -27,8 +28,6 @@ int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out)
         ctx->ws[slot] = nullptr;
         ctx->ws_bytes[slot] = 0;
         if (slot == WS_SYMVMAP) ctx->symv_map_n = -1;
-        if (slot == WS_SYMVFUSE) ctx->symv_fuse_n = -1;
-        if (slot == WS_FUSE3) ctx->fuse3_n = -1;
     }
     const size_t sz = (bytes + 4095) & ~(size_t)4095;
     void *p = nullptr;
@@ -47,11 +46,22 @@ int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out)
 static size_t ctl_bytes(int64_t rows) { return PCTL_STAGE_OFFSET + 2 * sizeof(double) * (size_t)rows; }
 static double *ctl_rstage(gsyeig_ctx *ctx, PCtl *c) { return ctl_stage(c) + ctx->ctl_rows; }
 
-// zero counters, staging entries all STAGE_SENTINEL (all-ones bytes)
+// zero counters, the context's spin bound, staging entries all
+// STAGE_SENTINEL (all-ones bytes)
 static int ctl_init(gsyeig_ctx *ctx, PCtl *c, int64_t rows)
 {
     HIP_TRY(hipMemsetAsync(c, 0, PCTL_STAGE_OFFSET, ctx->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&c->spin, (int)ctx->spin_limit, 1, ctx->stream));
     HIP_TRY(hipMemsetAsync(ctl_stage(c), 0xFF, 2 * sizeof(double) * (size_t)rows, ctx->stream));
+    return 0;
+}
+
+// Forget expired waits of earlier work (stream-ordered): a synchronous
+// entry point then reports only the waits of its own kernels.
+static int ctl_clear_err(gsyeig_ctx *ctx)
+{
+    HIP_TRY(hipMemsetAsync(&ctx->ctl_n->err, 0, sizeof(unsigned), ctx->stream));
+    HIP_TRY(hipMemsetAsync(&ctx->ctl_t->err, 0, sizeof(unsigned), ctx->stream));
     return 0;
 }
 
@@ -82,9 +92,7 @@ static int ctl_check(gsyeig_ctx *ctx)
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (h[0] || h[1]) {
-        // a wait expired: restart both control blocks (and the fused sweep's
-        // sentinel partials) from a clean state
-        ctx->fuse3_n = -1;
+        // a wait expired: restart both control blocks from a clean state
         int rc;
         if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)))
             return rc;
@@ -108,7 +116,7 @@ static void opts_fill_defaults(gsyeig_opts *o)
     o->which = 0;
     o->invert = 0;
     o->tol = 1e-12;
-    o->max_steps = 0;  // 0 = min(n, 100 s + 2000)
+    o->max_steps = 0;  // 0 = default_max_steps(n, s)
     o->check_every = 25;
     o->seed = 6374;
     o->v0 = nullptr;
@@ -127,9 +135,19 @@ static int64_t mixed_block(int64_t n, int64_t s, const gsyeig_opts *o)
     return std::min<int64_t>(n, std::min<int64_t>(s + g, syev_small_max() / 2));
 }
 
+// Default cap on the Lanczos steps: 100 s + 2000, raised to 10 sqrt(n s)
+// for small s on large n (the steps a clustered spectrum needs grow like
+// sqrt(n s): about 4.5 sqrt(n s) for 80 % of the values in [0, 1]).
+static int64_t default_max_steps(int64_t n, int64_t s)
+{
+    const int64_t by_s = 100 * s + 2000;
+    const int64_t by_ns = (int64_t)(10.0 * sqrt((double)n * (double)s));
+    return std::min<int64_t>(n, std::max<int64_t>(by_s, by_ns));
+}
+
 static int64_t eff_max_steps(int64_t n, int64_t s, const gsyeig_opts *o)
 {
-    int64_t m = (o && o->max_steps > 0) ? o->max_steps : std::min<int64_t>(n, 100 * s + 2000);
+    int64_t m = (o && o->max_steps > 0) ? o->max_steps : default_max_steps(n, s);
     m = std::min<int64_t>(m, n);
     return std::max<int64_t>(m, std::min<int64_t>(s, n));
 }
@@ -250,44 +268,6 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
-    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse == 2 && fused_ki3_fits(n)) {
-        // KI1, then KI2 and KI3 in one cooperative launch
-        const int2 *items;
-        int ntiles;
-        double *Pr, *Pc;
-        TRY(symv_fused3_prepare(ctx, n, &items, &ntiles, &Pr, &Pc));
-        TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
-        if (sample) {
-            HIP_TRY(hipEventRecord(e[1], ctx->stream));
-            HIP_TRY(hipEventRecord(e[2], ctx->stream));
-        }
-        TRY(launch_trsv_w_t_symv((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], op.A,
-                                 op.lda, tmp, z, ctx->ctl_t, items, ntiles, Pr, Pc, ctx->stream));
-        if (sample) {
-            HIP_TRY(hipEventRecord(e[3], ctx->stream));
-            ctx->npev += 4;
-        }
-        return 0;
-    }
-    if (!op.f32 && ctx->trsv_block != 64 && ctx->symv_fuse == 1 && fused_symv_fits(n)) {
-        // KI1 with KI2 fused (one cooperative launch), then the fixed-order
-        // reduction of the tile partials
-        const int2 *items;
-        int ntiles;
-        double *Pr, *Pc;
-        TRY(symv_fused_prepare(ctx, n, &items, &ntiles, &Pr, &Pc));
-        TRY(launch_trsv_w_n_symv((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], w,
-                                 tmp, ctx->ctl_n, op.A, op.lda, items, ntiles, Pr, Pc, ctx->stream));
-        if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
-        TRY(launch_symv_reduce_tiles(Pr, Pc, n, z, ctx->stream));
-        if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
-        TRY(solve_t(ctx, n, op.U, op.ldu, op.Dinv, z, z));
-        if (sample) {
-            HIP_TRY(hipEventRecord(e[3], ctx->stream));
-            ctx->npev += 4;
-        }
-        return 0;
-    }
     if (op.f32)
         TRY(launch_trsv_w_n_f32(op.W32, op.ldw32, n, op.sb, w, tmp, ctx->ctl_n, ctx->stream));
     else
@@ -485,8 +465,8 @@ struct LzResult {
     float t_loop_ms, t_ritz_ms;
 };
 
-static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const LzOp &op,
-                    const gsyeig_opts *o, double *theta_out, double *Y, int64_t ldy, LzResult *res)
+static int lz_solve_body(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const LzOp &op,
+                         const gsyeig_opts *o, double *theta_out, double *Y, int64_t ldy, LzResult *res)
 {
     const int64_t mmax = std::max<int64_t>(eff_max_steps(n, s, o), std::min<int64_t>(nvec, n));
     const int64_t w0 = o->which ? nvec - s : 0;
@@ -622,14 +602,30 @@ static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const L
     HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     res->reorth_steps = (b.reorth == 0) ? m : nconv_h[1];
-    if (b.reorth == 2 && nconv_h[2] != 0) return GSYEIG_ENOCONV;  // basis lost semi-orthogonality
     TRY(prof_harvest(ctx));
     HIP_TRY(hipEventElapsedTime(&res->t_loop_ms, ctx->ev[6], ctx->ev[7]));
     HIP_TRY(hipEventElapsedTime(&res->t_ritz_ms, ctx->ev[7], ctx->ev[5]));
     res->steps = m;
     res->nconv = nconv;
-    TRY(ctl_check(ctx));
+    if (b.reorth == 2 && nconv_h[2] != 0) {  // basis lost semi-orthogonality: the Ritz vectors are not valid
+        res->nconv = 0;
+        return GSYEIG_ENOCONV;
+    }
     return 0;
+}
+
+// lz_solve_body with the chained sweeps' wait record: cleared before the
+// first sweep, read on every exit, so that an expired wait is reported
+// (GSYEIG_ESPIN, ahead of GSYEIG_ENOCONV) by the call whose kernels it hit.
+static int lz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const LzOp &op,
+                    const gsyeig_opts *o, double *theta_out, double *Y, int64_t ldy, LzResult *res)
+{
+    TRY(ctl_reserve(ctx, n));
+    TRY(ctl_clear_err(ctx));
+    const int rc = lz_solve_body(ctx, n, s, nvec, op, o, theta_out, Y, ldy, res);
+    const int crc = ctl_check(ctx);
+    if (crc == GSYEIG_ESPIN && (rc == 0 || rc == GSYEIG_ENOCONV)) return GSYEIG_ESPIN;
+    return rc ? rc : crc;
 }
 
 // Blocked right-looking Cholesky B = U^T U of the upper triangle in place
@@ -861,7 +857,20 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
         r.t_loop_ms = br.t_loop_ms;
         r.t_ritz_ms = br.t_ritz_ms;
     } else {
-        TRY(lz_solve(ctx, n, s, k, op, &o, theta_k, Y, ldy, &r));
+        const int lrc = lz_solve(ctx, n, s, k, op, &o, theta_k, Y, ldy, &r);
+        if (lrc && lrc != GSYEIG_ENOCONV) return lrc;
+        if (lrc == GSYEIG_ENOCONV) {  // no valid Ritz vectors to refine: report the Lanczos phase
+            float t;
+            HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
+            inf.t_ki_ms = r.t_loop_ms;
+            inf.t_ki5_ms = r.t_ritz_ms;
+            inf.steps = r.steps;
+            inf.converged = 0;
+            inf.reorth_steps = r.reorth_steps;
+            inf.eta_max = inf.eta_phase1 = HUGE_VAL;
+            if (info) *info = inf;
+            return GSYEIG_ENOCONV;
+        }
     }
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     TRY(launch_backsolve_f32(U32, ld32, n, k, Dinv, Y, ldy, ctx->stream));
@@ -995,7 +1004,6 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
     gsyeig_ctx *ctx = new (std::nothrow) gsyeig_ctx;
     if (!ctx) return GSYEIG_ENOMEM;
     memset(ctx, 0, sizeof(*ctx));
-    ctx->symv_fuse = 0;
     ctx->stream = (hipStream_t)hip_stream;
     ctx->symv_map_n = -1;
     ctx->trsv_block = 512;
@@ -1045,12 +1053,20 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
     return 0;
 }
 
-int gsyeig_set_fused_symv(gsyeig_ctx *ctx, int on)
+int gsyeig_set_spin_limit(gsyeig_ctx *ctx, unsigned limit)
 {
     if (!ctx) return -1;
-    if (on < 0 || on > 2) return -2;
-    ctx->symv_fuse = on;
+    ctx->spin_limit = limit;
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_n->spin, (int)limit, 1, ctx->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_t->spin, (int)limit, 1, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return 0;
+}
+
+int gsyeig_sync(gsyeig_ctx *ctx)
+{
+    if (!ctx) return -1;
+    return ctl_check(ctx);
 }
 
 int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t *bytes)
@@ -1247,8 +1263,9 @@ int gsyeig_lanczos(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64
         return (br.nconv >= s) ? 0 : GSYEIG_ENOCONV;
     }
     LzResult r{};
-    TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, U, ldu, Dinv), &o, theta, Y, ldy, &r));
+    const int lrc = lz_solve(ctx, n, s, s, op_fp64(A, lda, U, ldu, Dinv), &o, theta, Y, ldy, &r);
     if (steps_out) *steps_out = r.steps;
+    if (lrc) return lrc;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
 }
 
@@ -1364,7 +1381,8 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
         r.t_loop_ms = br.t_loop_ms;
         r.t_ritz_ms = br.t_ritz_ms;
     } else {
-        TRY(lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r));
+        const int lrc = lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r);
+        if (lrc && lrc != GSYEIG_ENOCONV) return lrc;  // ENOCONV: finish, report in info
     }
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
@@ -1427,10 +1445,52 @@ int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
     float *W32 = (float *)p;
     TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
     TRY(launch_make_w_f32(U, ldu, n, Dinv, sb, W32, ldw, ctx->stream));
+    TRY(ctl_clear_err(ctx));
     if (trans == 0)
         TRY(launch_trsv_w_n_f32(W32, ldw, n, sb, b, x, ctx->ctl_n, ctx->stream));
     else
         TRY(launch_trsv_w_t_f32(W32, ldw, n, sb, b, x, ctx->ctl_t, ctx->stream));
+    return ctl_check(ctx);
+}
+
+int gsyeig_apply_op_lp(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t lda, const float *U, int64_t ldu,
+                       const double *w, double *z)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!U) return -5;
+    if (ldu < n) return -6;
+    if (!w) return -7;
+    if (!z) return -8;
+    TRY(ctl_reserve(ctx, n));
+    void *p;
+    TRY(ws_get(ctx, WS_DINV, tri_aux_bytes(n), &p));
+    double *Dinv = (double *)p;
+    TRY(ws_get(ctx, WS_SB, trsv_w_side_bytes(n), &p));
+    double *sb = (double *)p;
+    const int64_t ldw = round_ld(n);
+    TRY(ws_get(ctx, WS_W, sizeof(float) * (size_t)ldw * (size_t)n, &p));
+    float *W32 = (float *)p;
+    TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
+    TRY(launch_make_w_f32(U, ldu, n, Dinv, sb, W32, ldw, ctx->stream));
+    TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
+    double *tmp = (double *)p;
+    if (w == z) {  // the first sweep reads w while the last one writes z
+        TRY(ws_get(ctx, WS_TMP1, sizeof(double) * (size_t)n, &p));
+        TRY(launch_copy(w, (double *)p, n, ctx->stream));
+        w = (const double *)p;
+    }
+    LzOp op{};
+    op.f32 = 1;
+    op.Dinv = Dinv;
+    op.A32 = A; op.lda32 = lda;
+    op.U32 = U; op.ldu32 = ldu;
+    op.W32 = W32; op.ldw32 = ldw;
+    op.sb = sb;
+    TRY(ctl_clear_err(ctx));
+    TRY(apply_op(ctx, n, op, w, z, tmp));
     return ctl_check(ctx);
 }
 

@@ -419,6 +419,37 @@ __global__ __launch_bounds__(256) void k_symv_reduce(const double *__restrict__ 
 
 }  // namespace
 
+// Launch of the tile pass over the work list `items` (nitems runs of up to
+// SYMV_CH tiles), partials into Pr (nblk x maxch x 64) and Pc (nblk x nblk
+// x 64); the kernel variant follows the storage type and alignment of A.
+template <typename T>
+static int symv_tiles_launch(hipStream_t st, int64_t n, const T *A, int64_t lda, const double *x, const int2 *items,
+                             int64_t nitems, double *pr, double *pc, int maxch)
+{
+    const int nblk = (int)cdiv(n, NB);
+    // FP32 storage with 16-byte rows of 4: the quad-load kernel (measured
+    // 0.441 ms against 0.547 ms for the pair-load one at n = 32768, MI355X)
+    const bool quad = sizeof(T) == 4 && lda % 4 == 0 && n % 4 == 0;
+    const dim3 grid((unsigned)nitems);
+    if constexpr (sizeof(T) == 8) {
+        // 16-byte column pairs when rows and n are even (measured 0.203 ms
+        // against 0.230 ms for the 8-byte kernel at n = 16384, MI355X)
+        if (lda % 2 == 0 && n % 2 == 0)
+            hipLaunchKernelGGL(k_symv_tiles_q<SYMV_CH>, grid, dim3(256), 0, st, A, lda, n, nblk, maxch, x, items, pr,
+                               pc);
+        else
+            hipLaunchKernelGGL(k_symv_tiles, grid, dim3(256), 0, st, A, lda, n, nblk, maxch, x, items, pr, pc);
+    } else if (quad)
+        hipLaunchKernelGGL(k_symv_tiles_f32q<SYMV_CH>, grid, dim3(256), 0, st, A, lda, n, nblk, maxch, x, items, pr,
+                           pc);
+    else if (lda % 2 == 0)
+        hipLaunchKernelGGL(k_symv_tiles_f32<true>, grid, dim3(256), 0, st, A, lda, n, nblk, maxch, x, items, pr, pc);
+    else
+        hipLaunchKernelGGL(k_symv_tiles_f32<false>, grid, dim3(256), 0, st, A, lda, n, nblk, maxch, x, items, pr,
+                           pc);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
 // The tile pass of y = A x: partials into Pr / Pc (maxch chunk slots of
 // SYMV_CH tiles per block row), summed by k_symv_reduce or by the KI3 sweep.
 template <typename T>
@@ -426,9 +457,6 @@ static int symv_tiles_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, con
                         double **Pc_out, int *maxch_out)
 {
     const int nblk = (int)cdiv(n, NB);
-    // FP32 storage with 16-byte rows of 4: the quad-load kernel (measured
-    // 0.441 ms against 0.547 ms for the pair-load one at n = 32768, MI355X)
-    const bool quad = sizeof(T) == 4 && lda % 4 == 0 && n % 4 == 0;
     const int ch = SYMV_CH;
     const int maxch = (int)cdiv(nblk, ch);
     int rc;
@@ -448,26 +476,9 @@ static int symv_tiles_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, con
     if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * maxch * NB, &pr))) return rc;
     if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &pc))) return rc;
     const int2 *items = (const int2 *)ctx->ws[WS_SYMVMAP];
-    const dim3 grid((unsigned)ctx->symv_items);
-    if constexpr (sizeof(T) == 8) {
-        // 16-byte column pairs when rows and n are even (measured 0.203 ms
-        // against 0.230 ms for the 8-byte kernel at n = 16384, MI355X)
-        if (lda % 2 == 0 && n % 2 == 0)
-            hipLaunchKernelGGL(k_symv_tiles_q<SYMV_CH>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x,
-                               items, (double *)pr, (double *)pc);
-        else
-            hipLaunchKernelGGL(k_symv_tiles, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
-                               (double *)pr, (double *)pc);
-    } else if (quad)
-        hipLaunchKernelGGL(k_symv_tiles_f32q<SYMV_CH>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
-                           (double *)pr, (double *)pc);
-    else if (lda % 2 == 0)
-        hipLaunchKernelGGL(k_symv_tiles_f32<true>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x, items,
-                           (double *)pr, (double *)pc);
-    else
-        hipLaunchKernelGGL(k_symv_tiles_f32<false>, grid, dim3(256), 0, ctx->stream, A, lda, n, nblk, maxch, x,
-                           items, (double *)pr, (double *)pc);
-    if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    if ((rc = symv_tiles_launch<T>(ctx->stream, n, A, lda, x, items, ctx->symv_items, (double *)pr, (double *)pc,
+                                   maxch)))
+        return rc;
     *Pr_out = (double *)pr;
     *Pc_out = (double *)pc;
     *maxch_out = maxch;
@@ -483,41 +494,6 @@ static int launch_symv_t(gsyeig_ctx *ctx, int64_t n, const T *A, int64_t lda, co
     const int nblk = (int)cdiv(n, NB);
     hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, ctx->stream, (const double *)pr,
                        (const double *)pc, nblk, maxch, n, y, SYMV_CH);
-    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
-}
-
-// Work list of the fused KI1 + KI2 sweep: single 64x64 tiles (I, J >= I) of
-// the upper triangle, block rows from the bottom (the order of the sweep);
-// per-tile row partials (maxch = nblk).
-int symv_fused_prepare(gsyeig_ctx *ctx, int64_t n, const int2 **items, int *ntiles, double **Pr, double **Pc)
-{
-    const int nblk = (int)cdiv(n, NB);
-    int rc;
-    void *p;
-    const size_t cnt = (size_t)nblk * (nblk + 1) / 2;
-    if (ctx->symv_fuse_n != n) {
-        std::vector<int2> it;
-        it.reserve(cnt);
-        for (int I = nblk - 1; I >= 0; --I)
-            for (int J = I; J < nblk; ++J) it.push_back(make_int2(I, J));
-        if ((rc = ws_get(ctx, WS_SYMVFUSE, it.size() * sizeof(int2), &p))) return rc;
-        HIP_TRY(hipMemcpyAsync(p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        ctx->symv_fuse_n = n;
-    }
-    *items = (const int2 *)ctx->ws[WS_SYMVFUSE];
-    *ntiles = (int)cnt;
-    if ((rc = ws_get(ctx, WS_SYMV_PR, sizeof(double) * (size_t)nblk * nblk * NB, &p))) return rc;
-    *Pr = (double *)p;
-    if ((rc = ws_get(ctx, WS_SYMV_PC, sizeof(double) * (size_t)nblk * nblk * NB, &p))) return rc;
-    *Pc = (double *)p;
-    return 0;
-}
-
-int launch_symv_reduce_tiles(const double *Pr, const double *Pc, int64_t n, double *y, hipStream_t st)
-{
-    const int nblk = (int)cdiv(n, NB);
-    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, st, Pr, Pc, nblk, nblk, n, y, 1);
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
@@ -545,32 +521,3 @@ int launch_symv_partials_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t
     return symv_tiles_t<float>(ctx, n, A, lda, x, Pr, Pc, maxch);
 }
 
-// Queue and partials of the KI2 + KI3 fusion: tiles (I, J >= I), block rows
-// from the top; row and column partials (nblk x nblk x 64 each) filled with
-// the sentinel once (each launch leaves them so).
-int symv_fused3_prepare(gsyeig_ctx *ctx, int64_t n, const int2 **items, int *ntiles, double **Pr, double **Pc)
-{
-    const int nblk = (int)cdiv(n, NB);
-    const size_t cnt = (size_t)nblk * (nblk + 1) / 2;
-    const size_t itb = (cnt * sizeof(int2) + 255) & ~(size_t)255;
-    const size_t pb = sizeof(double) * (size_t)nblk * nblk * NB;
-    void *p;
-    int rc;
-    if ((rc = ws_get(ctx, WS_FUSE3, itb + 2 * pb, &p))) return rc;
-    char *base = (char *)p;
-    if (ctx->fuse3_n != n) {
-        std::vector<int2> it;
-        it.reserve(cnt);
-        for (int I = 0; I < nblk; ++I)
-            for (int J = I; J < nblk; ++J) it.push_back(make_int2(I, J));
-        HIP_TRY(hipMemcpyAsync(base, it.data(), cnt * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(hipMemsetAsync(base + itb, 0xFF, 2 * pb, ctx->stream));   // the sentinel: all ones
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        ctx->fuse3_n = n;
-    }
-    *items = (const int2 *)base;
-    *ntiles = (int)cnt;
-    *Pr = (double *)(base + itb);
-    *Pc = (double *)(base + itb + pb);
-    return 0;
-}

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(1024) void k_trsv_n(const double *__restrict__ U, i
                 const int t = t0 + g;
                 const int64_t col = (int64_t)(nblk - 1 - t) * NB + l;
                 const bool live = (t < ntile) && (col < n);
-                const double xv = settle(v[g], stage + colof(t), &ctl->err);
+                const double xv = settle(v[g], stage + colof(t), ctl);
                 const double xj = live ? xv : 0.0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[r] = fma(cur[g][r], xj, acc[r]);
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_trsv_n(const double *__restrict__ U, i
     if (has_next) {
         const int64_t cn = (int64_t)(I + 1) * NB + l;
         const int64_t cc = cn < n ? cn : n - 1;
-        const double xv = settle(ld_bits(stage + cc), stage + cc, &ctl->err);
+        const double xv = settle(ld_bits(stage + cc), stage + cc, ctl);
         const double xn = (cn < n) ? xv : 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) part[r] = wave_sum(mrow[r] * xn);
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(1024) void k_trsv_t(const double *__restrict__ U, i
 #pragma unroll
                 for (int r = 0; r < 4; ++r) nxt[g][r] = U[(rr + r) * ldu + colc];
             }
-            const double zmine = settle(pv, stage + prow, &ctl->err);
+            const double zmine = settle(pv, stage + prow, ctl);
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
                 const bool live = (t0 + g < ntile);
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_trsv_t(const double *__restrict__ U, i
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (I > 0) {
         const int64_t rp = (int64_t)(I - 1) * NB + l;  // block I-1 is complete
-        const double xp = settle(ld_bits(stage + rp), stage + rp, &ctl->err);
+        const double xp = settle(ld_bits(stage + rp), stage + rp, ctl);
 #pragma unroll
         for (int r = 0; r < 4; ++r) part[r] = wave_sum(mrow[r] * xp);
     }

@@ -32,112 +32,10 @@ namespace {
 using namespace chain;
 
 // ------------------------------------------------------------------ KI1
-// KI2 fused into the KI1 sweep (optional, SYMV = true): once a workgroup has
-// published its 64 values, its four 256-thread quarters take 64x64 tiles
-// (I, J >= I) of A's upper triangle from a queue ordered by block row from
-// the bottom (the order in which the sweep publishes x), wait (bounded) for
-// x_I and x_J on the staging vector, and apply each tile both ways --
-// y_I += A_IJ x_J, and y_J += A_IJ^T x_I for J > I -- into per-tile
-// partials that k_symv_reduce sums in a fixed order.  The SYMV stream
-// thereby runs in the bandwidth the latency-bound sweep leaves idle.  The
-// waits are safe only if every workgroup is resident: the fused form is
-// launched cooperatively.
-struct SymvFuse {
-    const void *A; int64_t lda;
-    const int2 *items;   // (I, J) tiles in queue order
-    int ntiles;
-    double *Pr, *Pc;     // row partials [I][J - I][64], column partials [J][I][64]
-};
-
-constexpr int FUSE_GRAB = 16;  // tiles per queue ticket: 4 per quarter
-
-template <typename TA>
-__device__ __forceinline__ void symv_one_tile(const SymvFuse &sf, int64_t n, int nblk, double *stage, PCtl *ctl,
-                                              double (*s_sp)[4][NB], int t)
-{
-    const TA *A = (const TA *)sf.A;
-    const int tid = threadIdx.x;
-    const int qd = tid >> 8, qt = tid & 255, ql = qt & 63, qw = qt >> 6;
-    const int c = 16 * qw + (ql & 15), rg = ql >> 4;
-    const bool have = t < sf.ntiles;
-    int I = 0, J = 0;
-    if (have) {
-        const int2 it = sf.items[t];
-        I = it.x;
-        J = it.y;
-    }
-    const int64_t r0 = (int64_t)I * NB, col = (int64_t)J * NB + c;
-    const bool colok = have && col < n;
-    double a[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int64_t row = r0 + rg + 4 * q;
-        a[q] = (colok && row < n) ? (double)A[row * sf.lda + col] : 0.0;
-    }
-    const double *pj = stage + (colok ? col : 0);
-    const unsigned long long vj = ld_bits(pj);
-    unsigned long long vi[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int64_t row = r0 + rg + 4 * q;
-        vi[q] = ld_bits(stage + ((have && row < n) ? row : 0));
-    }
-    const double xj = colok ? settle(vj, pj, &ctl->err) : 0.0;
-    double acc[16], cs = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int64_t row = r0 + rg + 4 * q;
-        const double xi = (have && row < n) ? settle(vi[q], stage + row, &ctl->err) : 0.0;
-        acc[q] = a[q] * xj;
-        cs = fma(a[q], xi, cs);
-    }
-    // column part (J > I): sum over the tile's 64 rows
-    cs += __shfl_xor(cs, 16);
-    cs += __shfl_xor(cs, 32);
-    if (have && J > I && rg == 0) sf.Pc[((int64_t)J * nblk + I) * NB + c] = cs;
-    // row part: sum over the 16 columns of this lane group, then over the 4 waves
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        double v = acc[q];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        acc[q] = v;
-    }
-    if ((ql & 15) == 0) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) s_sp[qd][qw][rg + 4 * q] = acc[q];
-    }
-    __syncthreads();
-    if (have && qt < NB)
-        sf.Pr[((int64_t)I * nblk + (J - I)) * NB + qt] =
-            (s_sp[qd][0][qt] + s_sp[qd][1][qt]) + (s_sp[qd][2][qt] + s_sp[qd][3][qt]);
-    __syncthreads();
-}
-
-// Tickets of FUSE_GRAB tiles; the next ticket is taken while the current
-// tiles are processed, so the queue's atomic is off the critical path.
-template <typename TA>
-__device__ __forceinline__ void symv_tiles_phase(const SymvFuse &sf, int64_t n, int nblk, double *stage, PCtl *ctl,
-                                                 double (*s_sp)[4][NB], int *s_tk)
-{
-    const int tid = threadIdx.x, qd = tid >> 8;
-    if (tid == 0) s_tk[0] = (int)atomicAdd(&ctl->pad, (unsigned)FUSE_GRAB);
-    __syncthreads();
-    int cur = s_tk[0];
-    for (int round = 0; cur < sf.ntiles; ++round) {
-        if (tid == 0) s_tk[(round + 1) & 1] = (int)atomicAdd(&ctl->pad, (unsigned)FUSE_GRAB);
-#pragma unroll 1
-        for (int u = 0; u < FUSE_GRAB / 4; ++u) symv_one_tile<TA>(sf, n, nblk, stage, ctl, s_sp, cur + 4 * qd + u);
-        cur = s_tk[(round + 1) & 1];  // written before the last __syncthreads of the tiles
-    }
-}
-
-template <typename T, typename TA, bool SYMV>
+template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int64_t ldw, int64_t n, int nblk,
                                                    const double *__restrict__ Uinv, const double *b, double *x,
-                                                   PCtl *ctl, SymvFuse sf)
+                                                   PCtl *ctl)
 {
     __shared__ int s_blk, s_last;
     double *stage = ctl_stage(ctl);
@@ -213,7 +111,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int6
                     const int t = t0 + g;
                     const int64_t col = (int64_t)(nblk - 1 - t) * NB + l;
                     const bool live = (t < NT) && (col < n);
-                    sx[g * NB + l] = live ? settle(v[g], stage + colof(t), &ctl->err) : 0.0;
+                    sx[g * NB + l] = live ? settle(v[g], stage + colof(t), ctl) : 0.0;
                 }
             }
             __syncthreads();
@@ -239,88 +137,10 @@ __global__ __launch_bounds__(1024) void k_trsv_w_n(const T *__restrict__ W, int6
             x[row] = xi;
         }
     }
-    if constexpr (SYMV) {
-        __shared__ double s_sp[4][4][NB];
-        __shared__ int s_tk[2];
-        symv_tiles_phase<TA>(sf, n, nblk, stage, ctl, s_sp, s_tk);
-    }
     retire(ctl, stage, n, nblk, &s_last);
 }
 
 // ------------------------------------------------------------------ KI3
-// KI2 fused into the KI3 sweep (optional, SYMV = true; FP64): the sweep's
-// right-hand side A x is not an input.  Whenever the next group of far
-// values (or, before the link, the tiles its own rows need) is not yet
-// available, a workgroup applies 64x64 tiles of A's upper triangle, taken
-// from a queue ordered by block row from the top (the order in which the
-// sweep needs the rows), to the complete KI1 result.  Partial sums are
-// written once each as data-carrying values into buffers that hold the
-// sentinel between launches; the workgroup of row block K sums the N
-// partials of its 64 rows (bounded waits) and restores the sentinels.  The
-// chain's demand for A x is front-loaded exactly when most workgroups are
-// still waiting for their turn.  Cooperative launch (the waits need every
-// workgroup resident).
-struct FuseT {
-    const double *A; int64_t lda;
-    const int2 *items;   // (I, J >= I) tiles, block rows from the top
-    int ntiles;
-    double *Pr, *Pc;     // sentinel-initialised row / column partials
-    const double *xin;   // the complete KI1 result
-};
-
-// One queue round: each 256-thread quarter applies one tile.  WG-uniform.
-__device__ __forceinline__ void ki3_symv_round(const FuseT &ft, int64_t n, int nblk, PCtl *ctl,
-                                               double (*s_sp)[4][NB], int *s_q)
-{
-    const int tid = threadIdx.x;
-    const int qd = tid >> 8, qt = tid & 255, ql = qt & 63, qw = qt >> 6;
-    const int c = 16 * qw + (ql & 15), rg = ql >> 4;
-    if (tid == 0) s_q[0] = (int)atomicAdd(&ctl->pad, 4u);
-    __syncthreads();
-    const int t = s_q[0] + qd;
-    if (s_q[0] + 4 >= ft.ntiles) s_q[1] = 1;  // queue exhausted from now on (benign race: all write 1)
-    const bool have = t < ft.ntiles;
-    int I = 0, J = 0;
-    if (have) {
-        const int2 it = ft.items[t];
-        I = it.x;
-        J = it.y;
-    }
-    const int64_t r0 = (int64_t)I * NB, col = (int64_t)J * NB + c;
-    const bool colok = have && col < n;
-    double a[16], xi[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int64_t row = r0 + rg + 4 * q;
-        const bool rok = have && row < n;
-        a[q] = (colok && rok) ? ft.A[row * ft.lda + col] : 0.0;
-        xi[q] = rok ? ft.xin[row] : 0.0;
-    }
-    const double xj = colok ? ft.xin[col] : 0.0;
-    double cs = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cs = fma(a[q], xi[q], cs);
-    cs += __shfl_xor(cs, 16);
-    cs += __shfl_xor(cs, 32);
-    if (have && J > I && rg == 0)
-        st_bits(ft.Pc + ((int64_t)J * nblk + I) * NB + c, (unsigned long long)__double_as_longlong(cs));
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        double v = a[q] * xj;
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        if ((ql & 15) == 0) s_sp[qd][qw][rg + 4 * q] = v;
-    }
-    __syncthreads();
-    if (have && qt < NB) {
-        const double v = (s_sp[qd][0][qt] + s_sp[qd][1][qt]) + (s_sp[qd][2][qt] + s_sp[qd][3][qt]);
-        st_bits(ft.Pr + ((int64_t)I * nblk + (J - I)) * NB + qt, (unsigned long long)__double_as_longlong(v));
-    }
-    __syncthreads();
-}
-
 // KI3's right-hand side given as the SYMV tile partials instead of b
 // (Pr == nullptr: b is used): the workgroup of block row K sums the row parts
 // of K and the column parts of tiles (I, K), I < K, in the order of
@@ -330,24 +150,18 @@ struct RowSums {
     int maxch, ch;
 };
 
-template <typename T, bool SYMV>
+template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int64_t ldw, int64_t n, int nblk,
                                                    const double *__restrict__ UinvT,
                                                    const double *__restrict__ WLt, const double *b, double *x,
-                                                   PCtl *ctl, FuseT ft, RowSums rs)
+                                                   PCtl *ctl, RowSums rs)
 {
     __shared__ int s_blk, s_last;
     __shared__ double s_part[16][NB];
-    __shared__ double s_sp[SYMV ? 4 : 1][4][NB];
-    __shared__ double s_b[SYMV ? 16 : 1][NB];
-    __shared__ int s_q[4];   // ticket, queue exhausted, ready flag
     __shared__ double s_y[SBR];  // y values of a super-block, polled once per workgroup
     double *stage = ctl_stage(ctl);  // holds y
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-    if (tid == 0) {
-        s_blk = take_ticket(ctl, nblk);
-        s_q[1] = 0;
-    }
+    if (tid == 0) s_blk = take_ticket(ctl, nblk);
     __syncthreads();
     const int i = s_blk;
     const int S = i / TPS, loc = i % TPS;
@@ -388,24 +202,6 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
     if (ntile > 0) {
         auto rowof = [&](int t) { return (int64_t)((t < ntile) ? t : ntile - 1) * NB + 4 * w; };
         for (int t0 = 0; t0 < ntile; t0 += GRP) {
-            if constexpr (SYMV) {
-                // while the group's values are not yet published, work the queue
-                for (;;) {
-                    if (w == 0) {
-                        const int p = l & (4 * GRP - 1);
-                        const int64_t prow = (int64_t)((t0 + (p >> 2) < ntile) ? t0 + (p >> 2) : ntile - 1) * NB +
-                                             (p & 3);
-                        const bool ok = ld_bits(stage + prow) != STAGE_SENTINEL;
-                        const unsigned long long all = __ballot(ok);
-                        if (l == 0) s_q[2] = (all == ~0ull) ? 1 : 0;
-                    }
-                    __syncthreads();
-                    const int rdy = s_q[2], ex = s_q[1];
-                    __syncthreads();
-                    if (rdy || ex) break;
-                    ki3_symv_round(ft, n, nblk, ctl, s_sp, s_q);
-                }
-            }
             double cur[GRP][4];
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
@@ -418,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
             const int p = l & (4 * GRP - 1);
             const int64_t prow = rowof(t0 + (p >> 2)) + (p & 3);
             const unsigned long long pv = ld_bits(stage + prow);
-            const double zmine = settle_lazy(pv, stage + prow, &ctl->err);
+            const double zmine = settle_lazy(pv, stage + prow, ctl);
 #pragma unroll
             for (int g = 0; g < GRP; ++g) {
                 const bool live = (t0 + g < ntile);
@@ -433,32 +229,6 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
     // far column sums of this tile's 64 outputs, folded over the 16 waves at publication
     s_part[w][l] = acc;
     __syncthreads();
-    if constexpr (SYMV) {
-        // the rows of this tile need the tiles of block rows 0..i: work the
-        // queue until those have all been taken, then sum the N partials of
-        // the tile's 64 rows (waiting for any still in flight)
-        const int64_t N = nblk;
-        const int64_t need = (int64_t)(i + 1) * N - (int64_t)i * (i + 1) / 2;
-        for (;;) {
-            if (tid == 0) s_q[2] = (int)__hip_atomic_load(&ctl->pad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int64_t taken = s_q[2];
-            const int ex = s_q[1];
-            __syncthreads();
-            if (taken >= need || ex) break;
-            ki3_symv_round(ft, n, nblk, ctl, s_sp, s_q);
-        }
-        double sb = 0.0;
-        const int64_t nr = N - i;   // row partials of block row i
-        for (int64_t q = w; q < N; q += 16) {
-            double *pp = (q < nr) ? ft.Pr + ((int64_t)i * nblk + q) * NB + l
-                                  : ft.Pc + ((int64_t)i * nblk + (q - nr)) * NB + l;
-            sb += settle(ld_bits(pp), pp, &ctl->err);
-            st_bits(pp, STAGE_SENTINEL);
-        }
-        s_b[w][l] = sb;
-        __syncthreads();
-    }
     // the link: y_{S-1} through the rows of W_{S-1,S}^T
     double lk[4] = {0.0, 0.0, 0.0, 0.0};
     if (has_prev) {
@@ -474,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
             for (int c = 0; c < TPS; ++c) v[c] = ld_bits(stage + s0 - SBR + (int64_t)c * NB + l);
 #pragma unroll
             for (int c = 0; c < TPS; ++c)
-                s_y[c * NB + l] = settle(v[c], stage + s0 - SBR + (int64_t)c * NB + l, &ctl->err);
+                s_y[c * NB + l] = settle(v[c], stage + s0 - SBR + (int64_t)c * NB + l, ctl);
         }
         __syncthreads();
 #pragma unroll
@@ -492,15 +262,8 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
 #pragma unroll
         for (int q = 0; q < 16; ++q) f += s_part[q][4 * w + l];
         const double ye = f + ((l == 0) ? lk[0] : (l == 1) ? lk[1] : (l == 2) ? lk[2] : lk[3]);
-        double be;
-        if constexpr (SYMV) {
-            be = 0.0;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) be += s_b[q][4 * w + l];
-        } else {
-            const int r = 4 * w + l;
-            be = (e >= n) ? 0.0 : rs.Pr ? (s_rs[0][r] + s_rs[1][r]) + (s_rs[2][r] + s_rs[3][r]) : b[e];
-        }
+        const int r = 4 * w + l;
+        const double be = (e >= n) ? 0.0 : rs.Pr ? (s_rs[0][r] + s_rs[1][r]) + (s_rs[2][r] + s_rs[3][r]) : b[e];
         if (e < n) st_bits(stage + e, (unsigned long long)__double_as_longlong(be - ye));
     }
     // the product below must not be scheduled into the link above
@@ -520,7 +283,7 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
 #pragma unroll
             for (int c = 0; c < TPS; ++c) {
                 const int64_t kk = s0 + (int64_t)c * NB + l;
-                s_y[c * NB + l] = (c <= loc && kk < n) ? settle(rb[c], stage + kk, &ctl->err) : 0.0;
+                s_y[c * NB + l] = (c <= loc && kk < n) ? settle(rb[c], stage + kk, ctl) : 0.0;
             }
         }
         __syncthreads();
@@ -541,15 +304,6 @@ __global__ __launch_bounds__(1024) void k_trsv_w_t(const T *__restrict__ W, int6
             const int64_t e = c0 + 4 * w + l;
             const double xi = (l == 0) ? xo[0] : (l == 1) ? xo[1] : (l == 2) ? xo[2] : xo[3];
             if (e < n) x[e] = xi;
-        }
-    }
-    if constexpr (SYMV) {
-        for (;;) {
-            __syncthreads();
-            const int ex = s_q[1];
-            __syncthreads();
-            if (ex) break;
-            ki3_symv_round(ft, n, nblk, ctl, s_sp, s_q);
         }
     }
     retire(ctl, stage, n, nblk, &s_last);
@@ -709,8 +463,7 @@ static int trsv_w_n_t(const T *W, int64_t ldw, int64_t n, const double *sbw, con
                       hipStream_t st)
 {
     const int nblk = (int)cdiv(n, NB);
-    hipLaunchKernelGGL((k_trsv_w_n<T, T, false>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw, b, x, ctl,
-                       SymvFuse{});
+    hipLaunchKernelGGL((k_trsv_w_n<T>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw, b, x, ctl);
     return ok();
 }
 
@@ -720,8 +473,8 @@ static int trsv_w_t_t(const T *W, int64_t ldw, int64_t n, const double *sbw, con
 {
     const int nblk = (int)cdiv(n, NB);
     const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
-    hipLaunchKernelGGL((k_trsv_w_t<T, false>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw + nsb * blk,
-                       sbw + 2 * nsb * blk, b, x, ctl, FuseT{}, rs);
+    hipLaunchKernelGGL((k_trsv_w_t<T>), dim3(nblk), dim3(1024), 0, st, W, ldw, n, nblk, sbw + nsb * blk,
+                       sbw + 2 * nsb * blk, b, x, ctl, rs);
     return ok();
 }
 
@@ -741,77 +494,6 @@ int launch_trsv_w_n_f32(const float *W, int64_t ldw, int64_t n, const double *sb
                         PCtl *ctl, hipStream_t st)
 {
     return trsv_w_n_t<float>(W, ldw, n, sbw, b, x, ctl, st);
-}
-
-// KI1 with KI2 fused (FP64 W and A): x = U^-1 b and the tile partials of
-// A x, cooperative launch.  Returns GSYEIG_EHIP when the grid cannot be
-// co-resident (the caller then runs the two kernels apart).
-int fused_symv_fits(int64_t n)
-{
-    static int max_blocks = -1;
-    if (max_blocks < 0) {
-        int per_cu = 0, dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_trsv_w_n<double, double, true>,
-                                                         1024, 0) != hipSuccess)
-            max_blocks = 0;
-        else
-            max_blocks = per_cu * cus;
-    }
-    return cdiv(n, NB) <= max_blocks;
-}
-
-int fused_ki3_fits(int64_t n)
-{
-    static int max_blocks = -1;
-    if (max_blocks < 0) {
-        int per_cu = 0, dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_trsv_w_t<double, true>, 1024, 0) !=
-                hipSuccess)
-            max_blocks = 0;
-        else
-            max_blocks = per_cu * cus;
-    }
-    return cdiv(n, NB) <= max_blocks;
-}
-
-// KI2 and KI3 together: x = U^-T (A xin) (FP64 W and A), cooperative launch;
-// Pr, Pc must hold the sentinel (they are left holding it).
-int launch_trsv_w_t_symv(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *A, int64_t lda,
-                         const double *xin, double *x, PCtl *ctl, const int2 *items, int ntiles, double *Pr,
-                         double *Pc, hipStream_t st)
-{
-    if (!fused_ki3_fits(n)) return GSYEIG_EHIP;
-    int nblk = (int)cdiv(n, NB);
-    const int64_t nsb = cdiv(n, SBR), blk = (int64_t)SBR * SBR;
-    const double *UinvT = sbw + nsb * blk, *WLt = sbw + 2 * nsb * blk;
-    const double *bnull = nullptr;
-    FuseT ft{A, lda, items, ntiles, Pr, Pc, xin};
-    RowSums rs{};
-    void *args[] = {(void *)&W,     (void *)&ldw,   (void *)&n, (void *)&nblk, (void *)&UinvT, (void *)&WLt,
-                    (void *)&bnull, (void *)&x,     (void *)&ctl, (void *)&ft, (void *)&rs};
-    if (hipLaunchCooperativeKernel((const void *)k_trsv_w_t<double, true>, dim3(nblk), dim3(1024), args, 0, st) !=
-        hipSuccess)
-        return GSYEIG_EHIP;
-    return ok();
-}
-
-int launch_trsv_w_n_symv(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
-                         PCtl *ctl, const double *A, int64_t lda, const int2 *items, int ntiles, double *Pr,
-                         double *Pc, hipStream_t st)
-{
-    if (!fused_symv_fits(n)) return GSYEIG_EHIP;
-    int nblk = (int)cdiv(n, NB);
-    SymvFuse sf{A, lda, items, ntiles, Pr, Pc};
-    void *args[] = {(void *)&W, (void *)&ldw, (void *)&n, (void *)&nblk, (void *)&sbw, (void *)&b, (void *)&x,
-                    (void *)&ctl, (void *)&sf};
-    if (hipLaunchCooperativeKernel((const void *)k_trsv_w_n<double, double, true>, dim3(nblk), dim3(1024), args, 0,
-                                   st) != hipSuccess)
-        return GSYEIG_EHIP;
-    return ok();
 }
 
 int launch_trsv_w_t_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,

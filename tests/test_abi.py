@@ -78,7 +78,8 @@ def test_null_context_is_rejected_without_gpu(gs):
     assert gs.gsyeig_trsm_lp(None, 10, 1, 10, 0, 2, 1, 10, 1, 10) == -1
     assert gs.gsyeig_syev_small(None, 10, 1, 10, 2, 0, 1, 1, 10) == -1
     assert gs.gsyeig_refine(None, 10, 2, 4, 1, 10, 1, 10, 1, 10, None, 1, 10, 1, 1, 10)[0] == -1
-    assert gs.gsyeig_set_fused_symv(None, 1) == -1
+    assert gs.gsyeig_set_spin_limit(None, 1) == -1
+    assert gs.gsyeig_sync(None) == -1
     assert gs.gsyeig_destroy(None) == -1
     assert gs.lib().gsyeig_opts_default(None) == -1
 

@@ -185,14 +185,13 @@ def test_apply_op_matches_oracle_and_known_c(gs, ctx, torch, orc, n, block):
     assert np.max(np.abs(z - C @ w)) <= 1e-12 * np.max(np.abs(w)) * n ** 0.5
 
 
-@pytest.mark.parametrize("n", [64, 1000, 4097, 16384])
-def test_fused_symv_equals_separate_kernels(gs, ctx, torch, orc, n):
-    """KI2 fused into the KI1 sweep (mode 1) or into the KI3 sweep (mode 2;
-    cooperative launches, per-tile partials) against the kernels run apart:
-    the same operator up to the order of the tile sums, and against the
-    oracle (small n).  Mode 2 runs again after mode 0 (its sentinel partials
-    must survive other launches)."""
-    say("fused symv", n)
+@pytest.mark.parametrize("n", [65, 4097, 16384])
+def test_apply_op_equals_separate_calls_bitwise(gs, ctx, torch, n):
+    """The operator's KI3 takes KI2's tile partials and sums them itself, in
+    the order of the standalone SYMV's reduction, so gsyeig_apply_op must be
+    bit-for-bit U^-T (A (U^-1 w)) computed by three separate calls (FP64,
+    512-row super-blocks); the same for the FP32-storage sweeps."""
+    say("apply_op bitwise", n)
     assert gs.gsyeig_set_trsv_block(ctx, 512) == 0
     if n <= 4097:
         d = gen.known_spectrum(n, seed=115, stream=(n,))
@@ -200,21 +199,66 @@ def test_fused_symv_equals_separate_kernels(gs, ctx, torch, orc, n):
     else:
         d = gen.known_spectrum_device(n, seed=115, stream=(n,), device="cuda")
         A, U = d["A"], d["U"]
-    w = gen.rng(116, n).standard_normal(n)
-    wd = dev(torch, w)
-    out = {}
-    for on in (1, 2, 0, 2):
-        assert gs.gsyeig_set_fused_symv(ctx, on) == 0
-        zd = torch.empty(n, dtype=torch.float64, device="cuda")
-        for _ in range(3):  # the counters, staging and partials reset themselves between launches
-            assert gs.gsyeig_apply_op(ctx, n, A, n, U, n, wd, zd) == 0
-        out[on] = host(zd)
-    assert gs.gsyeig_set_fused_symv(ctx, 0) == 0
-    scale = np.max(np.abs(out[0]))
-    for on in (1, 2):
-        assert np.max(np.abs(out[on] - out[0])) <= 1e-13 * scale * max(1.0, n / 1024)
-        if n <= 4097:
-            assert np.max(np.abs(out[on] - orc.apply_ki(d["A"], d["U"], w))) <= 1e-12 * np.max(np.abs(w))
+    w = dev(torch, gen.rng(116, n).standard_normal(n))
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    t1 = torch.empty_like(z)
+    t2 = torch.empty_like(z)
+    t3 = torch.empty_like(z)
+    for _ in range(2):  # counters and staging reset themselves between launches
+        assert gs.gsyeig_apply_op(ctx, n, A, n, U, n, w, z) == 0
+        assert gs.gsyeig_trsv(ctx, n, U, n, 0, w, t1) == 0
+        assert gs.gsyeig_symv(ctx, n, A, n, t1, t2) == 0
+        assert gs.gsyeig_trsv(ctx, n, U, n, 1, t2, t3) == 0
+        assert gs.gsyeig_sync(ctx) == 0
+        assert torch.equal(z, t3)
+    # FP32 storage: the mixed-precision operator against its own three calls
+    A32 = A.float().contiguous()
+    U32 = torch.triu(U).float().contiguous()
+    z32 = torch.empty_like(z)
+    assert gs.gsyeig_trsv_lp(ctx, n, U32, n, 0, w, t1) == 0
+    assert gs.gsyeig_symv_lp(ctx, n, A32, n, t1, t2) == 0
+    assert gs.gsyeig_trsv_lp(ctx, n, U32, n, 1, t2, t3) == 0
+    assert gs.gsyeig_apply_op_lp(ctx, n, A32, n, U32, n, w, z32) == 0
+    assert torch.equal(z32, t3)
+
+
+def test_expired_wait_is_reported_once(gs, ctx, torch):
+    """A chained wait that runs out is reported as GSYEIG_ESPIN by the call
+    whose kernels it hit, and only by that call: a spin bound of one poll
+    (set from the host) forces expiries in a healthy sweep, every kernel
+    still finishes, and after the bound is restored the next calls succeed
+    with correct results."""
+    n = 8192
+    say("espin", n)
+    assert gs.gsyeig_set_trsv_block(ctx, 512) == 0
+    d = gen.known_spectrum(2048, seed=117)
+    U32 = dev(torch, np.triu(d["U"])).float().contiguous()
+    U32 = torch.block_diag(U32, U32, U32, U32)
+    Uh = U32.double().cpu().numpy()
+    b = dev(torch, gen.rng(118).standard_normal(n))
+    x = torch.empty_like(b)
+    assert gs.gsyeig_set_spin_limit(ctx, 1) == 0
+    rc = gs.gsyeig_trsv_lp(ctx, n, U32, n, 1, b, x)
+    assert gs.gsyeig_set_spin_limit(ctx, 0) == 0
+    assert rc == gs.GSYEIG_ESPIN
+    # record cleared and the control blocks reset: the next calls are clean
+    assert gs.gsyeig_sync(ctx) == 0
+    for trans in (0, 1):
+        assert gs.gsyeig_trsv_lp(ctx, n, U32, n, trans, b, x) == 0
+        xr = host(x)
+        Ut = Uh if trans == 0 else Uh.T
+        res = Ut @ xr - host(b)
+        assert np.max(np.abs(res)) <= 1e-5 * np.max(np.abs(host(b)))
+    # asynchronous calls report through gsyeig_sync
+    Ud = U32.double().contiguous()
+    assert gs.gsyeig_set_spin_limit(ctx, 1) == 0
+    assert gs.gsyeig_trsv(ctx, n, Ud, n, 1, b, x) == 0
+    assert gs.gsyeig_sync(ctx) == gs.GSYEIG_ESPIN
+    assert gs.gsyeig_set_spin_limit(ctx, 0) == 0
+    assert gs.gsyeig_sync(ctx) == 0
+    assert gs.gsyeig_trsv(ctx, n, Ud, n, 1, b, x) == 0
+    assert gs.gsyeig_sync(ctx) == 0
+    assert np.max(np.abs(Uh.T @ host(x) - host(b))) <= 1e-10 * np.max(np.abs(host(b)))
 
 
 # --------------------------------------------------------------- KI4

@@ -291,6 +291,51 @@ def test_metrics_on_exact_and_perturbed_pairs(orc):
     assert m2["eta_max"] > 1e-10 and m2["e_lam"] > 1e-9
 
 
+def test_metrics_hand_computed_2x2(orc):
+    """eta_i, rho_F, omega and e_lam on a 2 x 2 pencil worked by hand (the
+    definitions of the accuracy metrics of Tables 3 and 7 plus the per-pair
+    backward error).  The pairs are not eigenpairs, ||x_i|| != 1,
+    ||A||_F != ||A||_2 and ||B||_F != ||B||_2, so dropping ||x_i|| from eta,
+    a 2-norm in place of a Frobenius norm, lambda in place of |lambda|, or
+    the wrong normaliser of rho_F each changes a value below.
+
+    A = [[2, 1], [1, 2]]  (||A||_F = sqrt 10, ||A||_2 = 3)
+    B = diag(4, 1)        (||B||_F = sqrt 17, ||B||_2 = 4)
+    x_1 = (1, 1), x_2 = (0, 2);  lam = (-1, 2)
+    r_1 = A x_1 + B x_1 = (3, 3) + (4, 1) = (7, 4)   ||r_1|| = sqrt 65
+    r_2 = A x_2 - 2 B x_2 = (2, 4) - (0, 4) = (2, 0) ||r_2|| = 2
+    X^T B X = [[5, 2], [2, 4]]  ->  I - X^T B X = [[-4, -2], [-2, -3]]
+    """
+    A = np.array([[2.0, 1.0], [1.0, 2.0]])
+    B = np.diag([4.0, 1.0])
+    X = np.array([[1.0, 1.0], [0.0, 2.0]])  # rows are x_1, x_2
+    lam = np.array([-1.0, 2.0])
+    m = orc.metrics(A, B, lam, X, lam_ref=np.array([-1.5, 2.5]))
+    r10, r17 = math.sqrt(10.0), math.sqrt(17.0)
+    eta1 = math.sqrt(65.0) / ((r10 + 1.0 * r17) * math.sqrt(2.0))
+    eta2 = 2.0 / ((r10 + 2.0 * r17) * 2.0)
+    assert m["eta"][0] == pytest.approx(eta1, rel=1e-14)
+    assert m["eta"][1] == pytest.approx(eta2, rel=1e-14)
+    assert m["eta_max"] == pytest.approx(max(eta1, eta2), rel=1e-14)
+    assert m["rho_F"] == pytest.approx(math.sqrt(65.0 + 4.0) / r17, rel=1e-14)
+    assert m["omega"] == pytest.approx(math.sqrt(33.0), rel=1e-14)
+    assert m["omega_paper"] == pytest.approx(math.sqrt(33.0) / r17, rel=1e-14)
+    assert m["e_lam"] == pytest.approx(0.5 / 2.5, rel=1e-14)
+
+
+def test_metrics_hand_computed_normaliser_max(orc):
+    """rho_F divides by max(||A||_F, ||B||_F): with ||A||_F > ||B||_F the
+    divisor switches to ||A||_F.  A = diag(3, 4) (||A||_F = 5), B = I
+    (||B||_F = sqrt 2); x_1 = e_1, lam_1 = 1: r_1 = (2, 0), eta_1 =
+    2 / (5 + sqrt 2), rho_F = 2 / 5, omega = 0."""
+    A = np.diag([3.0, 4.0])
+    B = np.eye(2)
+    m = orc.metrics(A, B, np.array([1.0]), np.array([[1.0, 0.0]]))
+    assert m["rho_F"] == pytest.approx(0.4, rel=1e-15)
+    assert m["eta_max"] == pytest.approx(2.0 / (5.0 + math.sqrt(2.0)), rel=1e-15)
+    assert m["omega"] == 0.0
+
+
 def test_splitmix64_published_vector():
     # first outputs of SplitMix64 seeded with 0 (x = 0; next() adds the golden gamma first)
     i = np.arange(1, 4, dtype=np.uint64)
