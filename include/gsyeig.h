@@ -60,6 +60,8 @@ extern "C" {
 #define GSYEIG_EHIP 0x40000001
 #define GSYEIG_ESPIN 0x40000002
 #define GSYEIG_ENOMEM 0x40000003
+#define GSYEIG_ETOOBIG 0x40000004
+#define GSYEIG_NOALLOC_MAX_N 16384
 #define GSYEIG_MAX_STREAMS 16
 
 typedef struct gsyeig_ctx gsyeig_ctx;
@@ -235,6 +237,26 @@ int gsyeig_trsv(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, int tr
  * alias.  Asynchronous. */
 int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *x,
                 double *y);
+
+/* KI2 for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x
+ * exactly as gsyeig_symv computes it (same kernels, same summation order,
+ * so the two agree bit for bit), enqueued on `hip_stream` (a hipStream_t,
+ * NULL = the null stream) with no context and no allocation.  Its scratch
+ * (the tile work list and the per-tile partial sums) lives in a file-scope
+ * device array of about 42 MB that each GPU the library runs on holds until
+ * the process ends; n is limited to GSYEIG_NOALLOC_MAX_N (16384), larger n
+ * returns GSYEIG_ETOOBIG.  Every scratch value is written before it is read
+ * in each call.  All calls on one GPU share that GPU's array, so calls that
+ * overlap in time on one GPU (different streams or host threads) race;
+ * serialise them.  The array's device address is resolved on the first call
+ * on each device (or by gsyeig_create there), which loads the library's code
+ * object if the runtime has not yet done so: make one call, or create a
+ * context, at set-up.  A (row-major, lda >= n) is read as by gsyeig_symv
+ * (upper block triangle, diagonal tiles in full); x and y must not alias.
+ * Asynchronous.  Returns 0, -2 (n < 1), -3..-6 (NULL A, lda < n, NULL x,
+ * NULL y), GSYEIG_ETOOBIG or GSYEIG_EHIP. */
+int gsyeig_symv_noalloc(void *hip_stream, int64_t n, const double *A, int64_t lda, const double *x, double *y);
 
 /* KI1-KI3: z = U^-T (A (U^-1 w)) = C w, the implicit operator of variant KI
  * (Section 2.3).  z may alias w.  Asynchronous. */

@@ -22,11 +22,13 @@ GSYEIG_ENOCONV = 0x40000000
 GSYEIG_EHIP = 0x40000001
 GSYEIG_ESPIN = 0x40000002
 GSYEIG_ENOMEM = 0x40000003
+GSYEIG_ETOOBIG = 0x40000004
+GSYEIG_NOALLOC_MAX_N = 16384
 
 # every entry point declared in include/gsyeig.h
 EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
-    "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_apply_op",
+    "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_symv_noalloc", "gsyeig_apply_op",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
     "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_sync", "gsyeig_solve_batched",
     "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_apply_op_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
@@ -45,7 +47,8 @@ def _describe(rc: int) -> str:
     if rc < 0:
         return f"illegal argument {-rc}"
     return {GSYEIG_ENOCONV: "not converged", GSYEIG_EHIP: "HIP error",
-            GSYEIG_ESPIN: "persistent-kernel wait expired", GSYEIG_ENOMEM: "out of device memory"}.get(
+            GSYEIG_ESPIN: "persistent-kernel wait expired", GSYEIG_ENOMEM: "out of device memory",
+            GSYEIG_ETOOBIG: "size beyond the entry point's fixed scratch"}.get(
         rc, f"leading minor {rc} of B not positive definite")
 
 
@@ -107,6 +110,7 @@ def lib():
                                I64, ctypes.POINTER(gsyeig_info)], I),
             "gsyeig_trsv": ([P, I64, P, I64, I, P, P], I),
             "gsyeig_symv": ([P, I64, P, I64, P, P], I),
+            "gsyeig_symv_noalloc": ([P, I64, P, I64, P, P], I),
             "gsyeig_apply_op": ([P, I64, P, I64, P, I64, P, P], I),
             "gsyeig_lanczos_run": ([P, I64, I64, P, I64, P, I64, P, P, P, P, I64], I),
             "gsyeig_tridiag_eig": ([P, I64, P, P, I64, I, P, P, I64], I),
@@ -191,6 +195,10 @@ def gsyeig_trsv(ctx, n, U, ldu, trans, b, x) -> int:
 
 def gsyeig_symv(ctx, n, A, lda, x, y) -> int:
     return lib().gsyeig_symv(ctx, n, _p(A), lda, _p(x), _p(y))
+
+
+def gsyeig_symv_noalloc(hip_stream, n, A, lda, x, y) -> int:
+    return lib().gsyeig_symv_noalloc(hip_stream, n, _p(A), lda, _p(x), _p(y))
 
 
 def gsyeig_apply_op(ctx, n, A, lda, U, ldu, w, z) -> int:

@@ -1019,6 +1019,8 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
         if (hipEventCreate(&ctx->pev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     int rc = ctl_reserve(ctx, 65536);
     if (rc) { delete ctx; return rc; }
+    void *scr;  // set-up of gsyeig_symv_noalloc on this device (its scratch array's address)
+    if ((rc = noalloc_scratch(&scr))) { delete ctx; return rc; }
     *ctx_out = ctx;
     return 0;
 }

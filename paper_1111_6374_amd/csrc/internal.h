@@ -104,6 +104,8 @@ struct gsyeig_ctx {
     } while (0)
 
 int ws_get(gsyeig_ctx *ctx, int slot, size_t bytes, void **out);
+// device address of gsyeig_symv_noalloc's scratch array on the current device
+int noalloc_scratch(void **out);
 int ctl_reserve(gsyeig_ctx *ctx, int64_t rows);
 
 // ---------------------------------------------------------------- launchers

@@ -9,6 +9,7 @@
 // Partial results go to a scratch area and a second kernel sums them in a
 // fixed order, so the result is bitwise reproducible run to run.  A may be
 // stored in FP64 or FP32 (mixed mode); arithmetic and vectors are FP64.
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -521,3 +522,90 @@ int launch_symv_partials_f32(gsyeig_ctx *ctx, int64_t n, const float *A, int64_t
     return symv_tiles_t<float>(ctx, n, A, lda, x, Pr, Pc, maxch);
 }
 
+// ------------------------------------------------------------ KI2, no allocation
+// gsyeig_symv_noalloc keeps the work list and the partials of the tile pass
+// in one file-scope device array sized for n <= GSYEIG_NOALLOC_MAX_N; every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel: its device address on the
+// current device comes from hipGetSymbolAddress, once per device.
+namespace {
+
+constexpr int64_t NA_NBLK = GSYEIG_NOALLOC_MAX_N / NB;
+constexpr int64_t NA_MAXCH = (NA_NBLK + SYMV_CH - 1) / SYMV_CH;
+constexpr size_t NA_ITEMS_BYTES = ((size_t)NA_NBLK * NA_MAXCH * sizeof(int2) + 255) & ~(size_t)255;
+constexpr size_t NA_PR_BYTES = (size_t)NA_NBLK * NA_MAXCH * NB * sizeof(double);
+constexpr size_t NA_PC_BYTES = (size_t)NA_NBLK * NA_NBLK * NB * sizeof(double);
+constexpr size_t NA_BYTES = NA_ITEMS_BYTES + NA_PR_BYTES + NA_PC_BYTES;
+static_assert(GSYEIG_NOALLOC_MAX_N % NB == 0, "the maximum is a whole number of tiles");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+void *na_ptr[NA_MAX_DEVICES];
+
+// The work list of the tile pass, the same runs in the same order as the
+// host-built list of launch_symv: row I holds ceil((nblk - I) / ch) runs.
+__global__ void k_symv_items(int2 *items, int nblk, int ch)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nblk) return;
+    int64_t off = 0;
+    for (int i = 0; i < I; ++i) off += (nblk - i + ch - 1) / ch;
+    for (int J0 = I, t = 0; J0 < nblk; J0 += ch, ++t) items[off + t] = make_int2(I, J0);
+}
+
+}  // namespace
+
+// Device address of the scratch array on the current device (resolved on
+// the first use per device; the lock keeps concurrent first calls apart).
+int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NA_MAX_DEVICES) return GSYEIG_EHIP;
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (!na_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return GSYEIG_EHIP;
+        }
+        na_ptr[dev] = p;
+    }
+    *out = na_ptr[dev];
+    return 0;
+}
+
+extern "C" int gsyeig_symv_noalloc(void *hip_stream, int64_t n, const double *A, int64_t lda, const double *x,
+                                   double *y)
+{
+    if (n < 1) return -2;
+    if (n > GSYEIG_NOALLOC_MAX_N) return GSYEIG_ETOOBIG;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!x) return -5;
+    if (!y) return -6;
+    void *base = nullptr;
+    int rc;
+    if ((rc = noalloc_scratch(&base))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nblk = (int)cdiv(n, NB);
+    const int maxch = (int)cdiv(nblk, SYMV_CH);
+    int64_t nitems = 0;
+    for (int I = 0; I < nblk; ++I) nitems += cdiv(nblk - I, SYMV_CH);
+    int2 *items = (int2 *)base;
+    double *pr = (double *)((char *)base + NA_ITEMS_BYTES);
+    double *pc = (double *)((char *)base + NA_ITEMS_BYTES + NA_PR_BYTES);
+    // every scratch value is written before it is read: nothing to clear
+    hipLaunchKernelGGL(k_symv_items, dim3((unsigned)cdiv(nblk, 64)), dim3(64), 0, st, items, nblk, SYMV_CH);
+    if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    if ((rc = symv_tiles_launch<double>(st, n, A, lda, x, items, nitems, pr, pc, maxch))) return rc;
+    hipLaunchKernelGGL(k_symv_reduce, dim3(nblk), dim3(256), 0, st, (const double *)pr, (const double *)pc, nblk,
+                       maxch, n, y, SYMV_CH);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
