@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--eta-tol", type=float, default=0.0, help="refinement target (0 = library default)")
     ap.add_argument("--reorth", type=int, default=-1,
                     help="re-orthogonalisation: 0 twice, 1 second pass when needed, 2 partial (-1 = default)")
+    ap.add_argument("--variant", choices=["ki", "ke"], default="ki",
+                    help="configs 0/1: the timed variant (KI: implicit operator, the default; KE: explicit C)")
+    ap.add_argument("--no-ke", action="store_true", help="configs 0/1: skip the KE solve timed beside KI")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -155,12 +158,15 @@ def main():
         opts.reorth = args.reorth
     if args.block > 1:
         opts.block = args.block
+    opts.variant = gs.GSYEIG_KE if args.variant == "ke" else gs.GSYEIG_KI
+    if args.variant == "ke":
+        cfg["label"] = cfg["label"].replace("single-vector KI", "single-vector KE (explicit C)")
     Lam = torch.empty(s, dtype=torch.float64, device=dev)
     X = torch.empty(s, n, dtype=torch.float64, device=dev)
 
-    def step():
+    def step(o=opts):
         B.copy_(B0)
-        rc, info = gs.gsyeig_solve(solver.ctx, n, s, A, n, B, n, opts, Lam, X, n)
+        rc, info = gs.gsyeig_solve(solver.ctx, n, s, A, n, B, n, o, Lam, X, n)
         if rc:
             raise gs.GsyeigError("gsyeig_solve", rc)
         return info
@@ -177,13 +183,41 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     for k, inf in enumerate(infos):
-        log(f"step {k}: total {inf.t_total_ms:.1f} ms (GS1 {inf.t_gs1_ms:.1f}, KI {inf.t_ki_ms:.1f}, "
-            f"KI5 {inf.t_ki5_ms:.1f}, BT1 {inf.t_bt1_ms:.1f}, check {inf.t_check_ms:.1f}) m={inf.steps}")
+        log(f"step {k}: total {inf.t_total_ms:.1f} ms (GS1 {inf.t_gs1_ms:.1f}, GS2 {inf.t_gs2_ms:.1f}, "
+            f"loop {inf.t_ki_ms:.1f}, KI5 {inf.t_ki5_ms:.1f}, BT1 {inf.t_bt1_ms:.1f}, check {inf.t_check_ms:.1f}) "
+            f"m={inf.steps}")
 
     # parity against the generator's known spectrum and the device FP64 check
     lam = Lam.cpu().numpy()
     e_lam = float(np.max(np.abs(lam - lam_true)) / np.max(np.abs(inst["lam"])))
     last = infos[-1]
+
+    # the other variant on the same input, timed beside the headline one
+    other = None
+    if not args.no_ke and opts.block == 1:
+        o2 = gs.gsyeig_opts_default()
+        o2.profile_every = args.profile_every
+        o2.reorth = opts.reorth
+        o2.variant = gs.GSYEIG_KI if opts.variant == gs.GSYEIG_KE else gs.GSYEIG_KE
+        name = "KI" if o2.variant == gs.GSYEIG_KI else "KE"
+        step(o2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        oi = [step(o2) for _ in range(2)]
+        torch.cuda.synchronize()
+        t_other = (time.perf_counter() - t0) / 2
+        lam2 = Lam.cpu().numpy()
+        i2 = oi[-1]
+        sm = sum(i.prof_samples for i in oi)
+        other = {"variant": name, "time_s": t_other, "steps": int(i2.steps),
+                 "stages_ms": {"gs1": i2.t_gs1_ms, "gs2": i2.t_gs2_ms, "loop": i2.t_ki_ms, "ki5": i2.t_ki5_ms,
+                               "bt1": i2.t_bt1_ms, "check": i2.t_check_ms},
+                 "op_ms_per_step": i2.t_ki_ms / max(i2.steps, 1),
+                 "symv_ms": sum(i.t_ki2_ms_sum for i in oi) / max(sm, 1),
+                 "e_lambda_vs_known": float(np.max(np.abs(lam2 - lam_true)) / np.max(np.abs(inst["lam"]))),
+                 "eta_max": i2.eta_max}
+        log(f"{name} beside: {t_other * 1e3:.1f} ms per solve (GS2 {i2.t_gs2_ms:.1f} ms, loop {i2.t_ki_ms:.1f} ms, "
+            f"m={i2.steps}), eta={i2.eta_max:.2e}")
 
     # dominant kernels: sampled per-launch durations inside the timed solves
     samples = sum(i.prof_samples for i in infos)
@@ -196,6 +230,10 @@ def main():
     trsv_gbs = (tri_bytes + vec_bytes) / (trsv_ms * 1e-3) / 1e9 if trsv_ms > 0 else None
     symv_gbs = (tri_bytes + vec_bytes) / (t2 * 1e-3) / 1e9 if t2 > 0 else None
 
+    ke = opts.variant == gs.GSYEIG_KE
+    if ke:  # the dominant kernel of KE is the SYMV with the explicit C (full read of the tile triangle)
+        sy_ms = t2
+        sy_gbs = (tri_bytes + vec_bytes) / (sy_ms * 1e-3) / 1e9 if sy_ms > 0 else None
     out = {
         "metric": "time-to-s-eigenpairs",
         "value": ms_per_step / 1e3,
@@ -212,18 +250,27 @@ def main():
         "config": {"workload": cfg["label"], "n": n, "s": s, "spectrum": cfg["law"], "prec": "fp64",
                    "block": int(opts.block), "lanczos_steps": int(last.steps), "reorth": int(opts.reorth),
                    "reorth_steps": int(last.reorth_steps), "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
-                     "traffic": measured_traffic("k_trsv_w", n, "fp64"),
-                     "kernel": "k_trsv_w_n/k_trsv_w_t (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
-                     "algorithmic_bytes_per_launch": tri_bytes + vec_bytes},
-        "kernels": {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
-                    "samples": samples},
-        "stages_ms": {"gs1": last.t_gs1_ms, "ki_loop": last.t_ki_ms, "ki5": last.t_ki5_ms,
+        "roofline": ({"bound": "hbm", "achieved": sy_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": (sy_gbs / HBM_PEAK_GBS) if sy_gbs else None, "traffic": None,
+                      "kernel": "k_symv_tiles_q + k_symv_reduce (KE's SYMV with C)", "avg_launch_ms": sy_ms,
+                      "algorithmic_bytes_per_launch": tri_bytes + vec_bytes} if ke else
+                     {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
+                      "traffic": measured_traffic("k_trsv_w", n, "fp64"),
+                      "kernel": "k_trsv_w_n/k_trsv_w_t (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
+                      "algorithmic_bytes_per_launch": tri_bytes + vec_bytes}),
+        "kernels": ({"symv_ms": t2, "symv_GBs": symv_gbs, "samples": samples} if ke else
+                    {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_tile_pass_ms": t2,
+                     "symv_tile_pass_GBs": symv_gbs, "samples": samples,
+                     "note": "KI2 is timed as its tile pass; its reduction runs inside KI3 (trsv_ms)"}),
+        "stages_ms": {"gs1": last.t_gs1_ms, "gs2": last.t_gs2_ms, "loop": last.t_ki_ms, "ki5": last.t_ki5_ms,
                       "bt1": last.t_bt1_ms, "check": last.t_check_ms, "total": last.t_total_ms},
         "parity": {"e_lambda_vs_known": e_lam, "eta_max": last.eta_max, "omega": last.omega,
                    "rho_F": last.rho_f, "pass": bool(e_lam <= 1e-10 and last.eta_max <= 1e-10)},
     }
+    out["config"]["variant"] = "KE" if ke else "KI"
+    if other:
+        out["beside"] = other
     solver.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -67,6 +67,7 @@ extern "C" {
 typedef struct gsyeig_ctx gsyeig_ctx;
 
 typedef enum { GSYEIG_FP64 = 0, GSYEIG_MIXED = 1 } gsyeig_prec;
+typedef enum { GSYEIG_KI = 0, GSYEIG_KE = 1 } gsyeig_variant;
 
 typedef struct {
     int prec;              /* GSYEIG_FP64 (every step in FP64), or GSYEIG_MIXED:  */
@@ -120,6 +121,12 @@ typedef struct {
                            /*   finer than 64 u_32 = 3.8e-6, the refinement      */
                            /*   finishes the pairs); 0 (default) = FP64           */
                            /*   accumulation of the FP32-stored matrices          */
+    int64_t variant;       /* GSYEIG_KI (default): Lanczos on the implicit       */
+                           /*   operator C = U^-T A U^-1, two triangular solves   */
+                           /*   and a symmetric product per step (Sec. 2.3, KI); */
+                           /*   GSYEIG_KE: C formed once (key GS2, 2 n^3 flops on */
+                           /*   the matrix cores), then one symmetric product per */
+                           /*   step (Sec. 2.3, KE).  KE: FP64, block = 1 only    */
 } gsyeig_opts;
 
 typedef struct {
@@ -162,6 +169,7 @@ typedef struct {
     int64_t reorth_steps;  /* single-vector Lanczos: steps that ran the         */
                            /*   conditional Gram-Schmidt (reorth 1: the second  */
                            /*   pass; 2: both passes; 0: every step)            */
+    double t_gs2_ms;       /* variant KE: forming C = U^-T A U^-1 (key GS2)     */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */
@@ -257,6 +265,17 @@ int gsyeig_symv(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const 
  * Asynchronous.  Returns 0, -2 (n < 1), -3..-6 (NULL A, lda < n, NULL x,
  * NULL y), GSYEIG_ETOOBIG or GSYEIG_EHIP. */
 int gsyeig_symv_noalloc(void *hip_stream, int64_t n, const double *A, int64_t lda, const double *x, double *y);
+
+/* GS2 (Eq. 3; Table 1, variants KE and TD of Section 2): the explicit
+ * standard-form matrix C = U^-T A U^-1 for the upper Cholesky factor U
+ * (row-major, ldu; only its upper triangle is read) and symmetric A (only
+ * read).  Two block triangular solves with all n columns as right-hand
+ * sides (2 n^3 flops of FP64 matrix-core products), a transpose between
+ * them, then C = (C + C^T) / 2.  C (n x n, ldc >= n) is exactly symmetric,
+ * so its column- and row-major storage coincide.  Uses n x n FP64 of
+ * context workspace besides C.  Asynchronous. */
+int gsyeig_form_c(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U, int64_t ldu,
+                  double *C, int64_t ldc);
 
 /* KI1-KI3: z = U^-T (A (U^-1 w)) = C w, the implicit operator of variant KI
  * (Section 2.3).  z may alias w.  Asynchronous. */

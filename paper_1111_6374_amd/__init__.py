@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgsyeig.so")
 
 GSYEIG_FP64 = 0
 GSYEIG_MIXED = 1
+GSYEIG_KI = 0
+GSYEIG_KE = 1
 GSYEIG_ENOCONV = 0x40000000
 GSYEIG_EHIP = 0x40000001
 GSYEIG_ESPIN = 0x40000002
@@ -28,7 +30,7 @@ GSYEIG_NOALLOC_MAX_N = 16384
 # every entry point declared in include/gsyeig.h
 EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
-    "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_symv_noalloc", "gsyeig_apply_op",
+    "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_symv_noalloc", "gsyeig_apply_op", "gsyeig_form_c",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
     "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_sync", "gsyeig_solve_batched",
     "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_apply_op_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
@@ -61,7 +63,8 @@ class gsyeig_opts(ctypes.Structure):
                 ("reorth", ctypes.c_int64),
                 ("basis", ctypes.c_int64),
                 ("keep", ctypes.c_int64),
-                ("block_acc32", ctypes.c_int64)]
+                ("block_acc32", ctypes.c_int64),
+                ("variant", ctypes.c_int64)]
 
 
 class gsyeig_info(ctypes.Structure):
@@ -74,7 +77,7 @@ class gsyeig_info(ctypes.Structure):
         ("block_applies", ctypes.c_int64), ("block_cols", ctypes.c_int64), ("restarts", ctypes.c_int64),
         ("basis", ctypes.c_int64), ("kept", ctypes.c_int64), ("t_rr_ms", ctypes.c_double),
         ("rr_count", ctypes.c_int64), ("cluster_fallbacks", ctypes.c_int64),
-        ("fallback_reason", ctypes.c_int64), ("reorth_steps", ctypes.c_int64)]
+        ("fallback_reason", ctypes.c_int64), ("reorth_steps", ctypes.c_int64), ("t_gs2_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -112,6 +115,7 @@ def lib():
             "gsyeig_symv": ([P, I64, P, I64, P, P], I),
             "gsyeig_symv_noalloc": ([P, I64, P, I64, P, P], I),
             "gsyeig_apply_op": ([P, I64, P, I64, P, I64, P, P], I),
+            "gsyeig_form_c": ([P, I64, P, I64, P, I64, P, I64], I),
             "gsyeig_lanczos_run": ([P, I64, I64, P, I64, P, I64, P, P, P, P, I64], I),
             "gsyeig_tridiag_eig": ([P, I64, P, P, I64, I, P, P, I64], I),
             "gsyeig_lanczos": ([P, I64, I64, P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P, P, I64,
@@ -203,6 +207,10 @@ def gsyeig_symv_noalloc(hip_stream, n, A, lda, x, y) -> int:
 
 def gsyeig_apply_op(ctx, n, A, lda, U, ldu, w, z) -> int:
     return lib().gsyeig_apply_op(ctx, n, _p(A), lda, _p(U), ldu, _p(w), _p(z))
+
+
+def gsyeig_form_c(ctx, n, A, lda, U, ldu, C, ldc) -> int:
+    return lib().gsyeig_form_c(ctx, n, _p(A), lda, _p(U), ldu, _p(C), ldc)
 
 
 def gsyeig_lanczos_run(ctx, n, k, A, lda, U, ldu, v0, alpha, beta, V, ldv) -> int:

@@ -252,6 +252,7 @@ struct LzOp {
     const float *U32; int64_t ldu32;
     const float *W32; int64_t ldw32;
     const double *sb;   // super-block inverses and link blocks of U~
+    const double *C; int64_t ldc;  // variant KE: the explicit C (the operator is one SYMV)
 };
 
 static LzOp op_fp64(const double *A, int64_t lda, const double *U, int64_t ldu, const double *Dinv)
@@ -268,6 +269,17 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
     sample = sample && ctx->npev + 4 <= 64;
     hipEvent_t *e = ctx->pev + ctx->npev;
     if (sample) HIP_TRY(hipEventRecord(e[0], ctx->stream));
+    if (op.C) {  // variant KE: z = C w (KI1 and KI3 are empty in the samples)
+        if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
+        TRY(launch_symv(ctx, n, op.C, op.ldc, w, w == z ? tmp : z));
+        if (w == z) TRY(launch_copy(tmp, z, n, ctx->stream));
+        if (sample) {
+            HIP_TRY(hipEventRecord(e[2], ctx->stream));
+            HIP_TRY(hipEventRecord(e[3], ctx->stream));
+            ctx->npev += 4;
+        }
+        return 0;
+    }
     if (op.f32)
         TRY(launch_trsv_w_n_f32(op.W32, op.ldw32, n, op.sb, w, tmp, ctx->ctl_n, ctx->stream));
     else
@@ -1013,7 +1025,7 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
         return GSYEIG_EHIP;
     }
     if (hipMalloc(&ctx->dscal, 4096) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 10; ++i)
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     for (int i = 0; i < 64; ++i)
         if (hipEventCreate(&ctx->pev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
@@ -1039,7 +1051,7 @@ int gsyeig_destroy(gsyeig_ctx *ctx)
     if (ctx->ctl_t) (void)hipFree(ctx->ctl_t);
     if (ctx->dscal) (void)hipFree(ctx->dscal);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 10; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     for (int i = 0; i < 64; ++i)
         if (ctx->pev[i]) (void)hipEventDestroy(ctx->pev[i]);
@@ -1100,6 +1112,7 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     if (o.reorth == 2)  // omega estimates; Gram matrix of the basis and its diagonal-block inverses
         b += sizeof(double) * ((size_t)(3 * (mmax + 8) + 8) + (size_t)mmax * (size_t)mmax +
                                (size_t)cdiv(mmax, NB) * NB * NB);
+    if (o.variant == GSYEIG_KE) b += 2 * sizeof(double) * (size_t)ldv * (size_t)n;  // C and its scratch
     if (o.invert) {
         b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
         if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
@@ -1182,6 +1195,27 @@ int gsyeig_apply_op(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, co
     void *p;
     TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
     return apply_op(ctx, n, op_fp64(A, lda, U, ldu, Dinv), w, z, (double *)p);
+}
+
+int gsyeig_form_c(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t lda, const double *U, int64_t ldu,
+                  double *C, int64_t ldc)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!U) return -5;
+    if (ldu < n) return -6;
+    if (!C) return -7;
+    if (ldc < n) return -8;
+    double *Dinv;
+    TRY(dinv_from_u(ctx, n, U, ldu, &Dinv));
+    const double *sb;
+    TRY(block_sb_fp64(ctx, n, U, ldu, Dinv, &sb));
+    const double *Wd = (ctx->trsv_block == 64) ? nullptr : (const double *)ctx->ws[WS_W];
+    void *pt;
+    TRY(ws_get(ctx, WS_CKE2, sizeof(double) * (size_t)round_ld(n) * (size_t)n, &pt));
+    return form_c(A, lda, U, ldu, Wd, round_ld(n), sb, n, C, ldc, (double *)pt, round_ld(n), ctx->stream);
 }
 
 int gsyeig_lanczos_run(gsyeig_ctx *ctx, int64_t n, int64_t k, const double *A, int64_t lda,
@@ -1330,7 +1364,8 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (!o.invert) ctx->n_fallback = ctx->fallback_why = 0;
     if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block < 1 || (o.invert != 0 && o.invert != 1) ||
         o.reorth < 0 || o.reorth > 2 ||
-        (o.which != 0 && o.which != 1))
+        (o.which != 0 && o.which != 1) || (o.variant != GSYEIG_KI && o.variant != GSYEIG_KE) ||
+        (o.variant == GSYEIG_KE && (o.prec != GSYEIG_FP64 || o.block != 1)))
         return -8;
     if (o.block > 1) TRY(blz_check_dims(n, s, o.prec == GSYEIG_MIXED ? mixed_block(n, s, &o) : s, &o));
     if (!Lambda) return -9;
@@ -1372,6 +1407,21 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
 
     LzResult r{};
     BlzResult br{};
+    LzOp lop = op_fp64(A, lda, B, ldb, Dinv);
+    if (o.variant == GSYEIG_KE) {
+        // GS2: C = U^-T A U^-1 with the block solves of the factor
+        const double *sb;
+        TRY(block_sb_fp64(ctx, n, B, ldb, Dinv, &sb));
+        const double *Wd = (ctx->trsv_block == 64) ? nullptr : (const double *)ctx->ws[WS_W];
+        const int64_t ldc = round_ld(n);
+        void *pc, *pt;
+        TRY(ws_get(ctx, WS_CKE, sizeof(double) * (size_t)ldc * (size_t)n, &pc));
+        TRY(ws_get(ctx, WS_CKE2, sizeof(double) * (size_t)ldc * (size_t)n, &pt));
+        TRY(form_c(A, lda, B, ldb, Wd, round_ld(n), sb, n, (double *)pc, ldc, (double *)pt, ldc, ctx->stream));
+        lop.C = (const double *)pc;
+        lop.ldc = ldc;
+    }
+    HIP_TRY(hipEventRecord(ctx->ev[8], ctx->stream));
     if (o.block > 1) {
         const double *sb;
         TRY(block_sb_fp64(ctx, n, B, ldb, Dinv, &sb));
@@ -1383,7 +1433,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
         r.t_loop_ms = br.t_loop_ms;
         r.t_ritz_ms = br.t_ritz_ms;
     } else {
-        const int lrc = lz_solve(ctx, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r);
+        const int lrc = lz_solve(ctx, n, s, s, lop, &o, Lambda, X, ldx, &r);
         if (lrc && lrc != GSYEIG_ENOCONV) return lrc;  // ENOCONV: finish, report in info
     }
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
@@ -1403,6 +1453,7 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     inf.normB_f = h[4];
     float t;
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[8])); inf.t_gs2_ms = t;
     inf.t_ki_ms = r.t_loop_ms;
     inf.t_ki5_ms = r.t_ritz_ms;
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;

@@ -65,6 +65,8 @@ enum WsSlot {
     WS_BLZ,        // block Lanczos: projected matrix, Ritz coefficients, blocks, kept Ritz vectors
     WS_PRO,        // omega estimates of the partial re-orthogonalisation (3 x (max_steps + 2))
     WS_PROG,       // Gram matrix V_m^T V_m of the semi-orthogonal basis and its Cholesky data
+    WS_CKE,        // variant KE: the explicit C = U^-T A U^-1 (n x n FP64)
+    WS_CKE2,       // variant KE: the second n x n buffer of its formation
     WS_COUNT
 };
 
@@ -82,7 +84,7 @@ struct gsyeig_ctx {
     unsigned spin_limit;  // polls per wait of the chained kernels (0 = SPIN_LIMIT)
     void *host_pinned;  // small pinned host staging area
     void *dscal;        // small device scratch (info codes, counters, check results)
-    hipEvent_t ev[8];
+    hipEvent_t ev[10];
     hipEvent_t pev[64];   // sampled per-kernel timing (4 per sampled step)
     int npev;             // events recorded since the last harvest
     int64_t prof_samples;
@@ -299,6 +301,13 @@ size_t blz_bytes(int64_t n, int64_t s, int64_t nvec, const gsyeig_opts *o);
 int blz_check_dims(int64_t n, int64_t s, int64_t nvec, const gsyeig_opts *o);
 int blz_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, const BlkOp &op, const gsyeig_opts *o,
               double *theta_out, double *Y, int64_t ldy, BlzResult *res);
+
+// GS2 of variant KE (k_ke.hip): C = U^-T A U^-1, column-major (= row-major,
+// C symmetric); W == nullptr: the solves use U with its super-block inverses
+int launch_transpose(const double *X, int64_t ldx, double *Y, int64_t ldy, int64_t n, hipStream_t st);
+int launch_symmetrise(double *C, int64_t ldc, int64_t n, hipStream_t st);
+int form_c(const double *A, int64_t lda, const double *U, int64_t ldu, const double *W, int64_t ldw,
+           const double *sb, int64_t n, double *C, int64_t ldc, double *T, int64_t ldt, hipStream_t st);
 
 // accuracy check
 int fro_parts(int64_t n);

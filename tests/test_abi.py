@@ -51,8 +51,8 @@ def test_version_and_defaults(gs):
     o = gs.gsyeig_opts_default()
     assert (o.prec, o.block, o.which, o.invert) == (0, 1, 0, 0)
     assert o.tol == 1e-12 and o.check_every == 25 and o.seed == 6374 and not o.v0
-    assert ctypes.sizeof(gs.gsyeig_opts) == 128 and o.profile_every == 0
-    assert (o.basis, o.keep, o.block_acc32) == (0, 0, 0)
+    assert o.profile_every == 0
+    assert (o.basis, o.keep, o.block_acc32, o.variant) == (0, 0, 0, gs.GSYEIG_KI)
     assert (o.eta_tol, o.refine_iters, o.refine_inner, o.guard, o.reorth) == (1e-10, 10, 20, 0, 2)
 
 
@@ -88,3 +88,27 @@ def test_binding_refuses_cpu_tensors(gs):
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         gs._p(torch.zeros(3, dtype=torch.float64))
+
+
+def test_binding_structs_match_the_header(gs, tmp_path):
+    """The ctypes mirrors of gsyeig_opts and gsyeig_info have the C layout:
+    sizes and every field offset, as a C compiler lays out the header."""
+    fields = {"gsyeig_opts": gs.gsyeig_opts, "gsyeig_info": gs.gsyeig_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st, cls in fields.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for name, _ in cls._fields_:
+            lines.append(f'printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    assert os.system(f"gcc -std=c11 -o {exe} {src}") == 0
+    got = {}
+    for ln in os.popen(str(exe)).read().splitlines():
+        st, name, val = ln.split()
+        got[(st, name)] = int(val)
+    for st, cls in fields.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)

@@ -1,5 +1,6 @@
 """Parity at the full benchmark size (n = 16384, s = 100, FP64), in the launch
-configuration the bench times.  The oracle cannot solve this size, so it
+configuration the bench times, for variant KI (the headline) and variant KE
+(explicit C).  The oracle cannot solve this size, so it
 checks what it can compute one by one: every eigenvalue against the
 generator's exact spectrum, and sampled pairs (x_i, lambda_i) through the
 oracle's own matrix-vector products (residual) and back-substitution
@@ -19,7 +20,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_full_size_known_spectrum(orc):
+@pytest.mark.parametrize("variant", ["KI", "KE"])
+def test_full_size_known_spectrum(orc, variant):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -30,9 +32,11 @@ def test_full_size_known_spectrum(orc):
     inst = gen.known_spectrum_device(n, "spaced", seed=gen.BASE_SEED + 1, stream=(1, 0, 0), device="cuda")
     A, B = inst["A"], inst["B"]
     B_h = B.cpu().numpy()
-    say("fullsize-solve", n, s)
+    say("fullsize-solve", n, s, variant)
+    o = gs.gsyeig_opts_default()
+    o.variant = gs.GSYEIG_KE if variant == "KE" else gs.GSYEIG_KI
     with gs.Solver() as sv:
-        lam, X, info = sv.solve(A, B, s)
+        lam, X, info = sv.solve(A, B, s, opts=o)
     torch.cuda.synchronize()
     assert info["rc"] == 0, info
     lam = lam.cpu().numpy()
