@@ -108,6 +108,10 @@ def main():
     ap.add_argument("--variant", choices=["ki", "ke"], default="ki",
                     help="configs 0/1: the timed variant (KI: implicit operator, the default; KE: explicit C)")
     ap.add_argument("--no-ke", action="store_true", help="configs 0/1: skip the KE solve timed beside KI")
+    ap.add_argument("--sweep-s", default="",
+                    help="comma-separated s values: time the variants (--sweep-variants) against s on the config's "
+                         "input (the shape of the paper's Figs. 1-2); one JSON line per point, no headline line")
+    ap.add_argument("--sweep-variants", default="ki,ke,td", help="variants of --sweep-s")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -132,6 +136,8 @@ def main():
         cfg["n"] = args.n or cfg["n"]
         cfg["s"] = args.s or cfg["s"]
         cfg["label"] += f" (reduced to n={cfg['n']} s={cfg['s']})"
+    if args.sweep_s:
+        return bench_sweep(args, cfg)
     if args.config == 4:
         return bench_batched(args, cfg)
     if args.config == 2:
@@ -276,6 +282,64 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, cfg):
+    """Time-to-s-eigenpairs against s for variants KI, KE and TD on one input
+    (the known-spectrum pencil of the configuration, FP64): the paper's
+    Figs. 1-2 plot the same quantity for its MD and DFT problems, where the
+    Krylov variants win for s up to a few per cent of n (Sec. 6).  Each point
+    is the median of --steps solves after one untimed solve of the same
+    variant and s."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1111_6374_amd as gs
+
+    n = cfg["n"]
+    svals = [int(v) for v in args.sweep_s.split(",") if v]
+    names = [v.strip().upper() for v in args.sweep_variants.split(",") if v.strip()]
+    code = {"KI": gs.GSYEIG_KI, "KE": gs.GSYEIG_KE, "TD": gs.GSYEIG_TD}
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating n={n} law={cfg['law']}")
+    inst = gen.known_spectrum_device(n, cfg["law"], seed=gen.BASE_SEED + args.config,
+                                     stream=(args.config, 0, 0), device=dev, keep_factors=False)
+    A, B0 = inst["A"], inst["B"]
+    lam_sorted = np.sort(inst["lam"])
+    scale = np.max(np.abs(inst["lam"]))
+    B = torch.empty_like(B0)
+    solver = gs.Solver()
+    rows = []
+    for s_ in svals:
+        Lam = torch.empty(s_, dtype=torch.float64, device=dev)
+        X = torch.empty(s_, n, dtype=torch.float64, device=dev)
+        for name in names:
+            o = gs.gsyeig_opts_default()
+            o.variant = code[name]
+            times, info = [], None
+            for k in range(1 + max(1, args.steps)):
+                B.copy_(B0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, info = gs.gsyeig_solve(solver.ctx, n, s_, A, n, B, n, o, Lam, X, n)
+                torch.cuda.synchronize()
+                if rc:
+                    raise gs.GsyeigError("gsyeig_solve", rc)
+                if k > 0:
+                    times.append(time.perf_counter() - t0)
+            e_lam = float(np.max(np.abs(Lam.cpu().numpy() - lam_sorted[:s_])) / scale)
+            row = {"n": n, "s": s_, "s_over_n": s_ / n, "variant": name, "time_s": float(np.median(times)),
+                   "steps": int(info.steps), "gs1_ms": info.t_gs1_ms, "gs2_ms": info.t_gs2_ms,
+                   "loop_ms": info.t_ki_ms, "ki5_ms": info.t_ki5_ms, "bt1_ms": info.t_bt1_ms,
+                   "e_lambda": e_lam, "eta_max": info.eta_max}
+            rows.append(row)
+            log(f"s={s_} ({100 * s_ / n:.2f} %) {name}: {row['time_s']:.3f} s (GS2 {info.t_gs2_ms:.0f} ms, "
+                f"loop/TD {info.t_ki_ms:.0f} ms, m={info.steps}) e_lam={e_lam:.1e} eta={info.eta_max:.1e}")
+            print(json.dumps(row), flush=True)
+    solver.close()
+    return rows
 
 
 def trsv_only(args, cfg):

@@ -67,7 +67,7 @@ extern "C" {
 typedef struct gsyeig_ctx gsyeig_ctx;
 
 typedef enum { GSYEIG_FP64 = 0, GSYEIG_MIXED = 1 } gsyeig_prec;
-typedef enum { GSYEIG_KI = 0, GSYEIG_KE = 1 } gsyeig_variant;
+typedef enum { GSYEIG_KI = 0, GSYEIG_KE = 1, GSYEIG_TD = 2 } gsyeig_variant;
 
 typedef struct {
     int prec;              /* GSYEIG_FP64 (every step in FP64), or GSYEIG_MIXED:  */
@@ -126,7 +126,12 @@ typedef struct {
                            /*   and a symmetric product per step (Sec. 2.3, KI); */
                            /*   GSYEIG_KE: C formed once (key GS2, 2 n^3 flops on */
                            /*   the matrix cores), then one symmetric product per */
-                           /*   step (Sec. 2.3, KE).  KE: FP64, block = 1 only    */
+                           /*   step (Sec. 2.3, KE); GSYEIG_TD: no Krylov method: */
+                           /*   C formed (GS2), reduced to tridiagonal form by    */
+                           /*   Householder reflectors, its s wanted pairs by     */
+                           /*   bisection and inverse iteration, back-transformed */
+                           /*   (Sec. 2.2, TD1-TD3; the dense comparator).  KE    */
+                           /*   and TD: FP64, block = 1, invert = 0 only          */
 } gsyeig_opts;
 
 typedef struct {
@@ -169,7 +174,10 @@ typedef struct {
     int64_t reorth_steps;  /* single-vector Lanczos: steps that ran the         */
                            /*   conditional Gram-Schmidt (reorth 1: the second  */
                            /*   pass; 2: both passes; 0: every step)            */
-    double t_gs2_ms;       /* variant KE: forming C = U^-T A U^-1 (key GS2)     */
+    double t_gs2_ms;       /* variants KE, TD: forming C = U^-T A U^-1 (GS2);   */
+                           /*   for TD, t_ki_ms holds TD1-TD3 (reduction,       */
+                           /*   tridiagonal eigenpairs, back-transformation)    */
+                           /*   and steps is 0                                  */
 } gsyeig_info;
 
 /* Library version string (host, static storage). */

@@ -20,6 +20,7 @@ GSYEIG_FP64 = 0
 GSYEIG_MIXED = 1
 GSYEIG_KI = 0
 GSYEIG_KE = 1
+GSYEIG_TD = 2
 GSYEIG_ENOCONV = 0x40000000
 GSYEIG_EHIP = 0x40000001
 GSYEIG_ESPIN = 0x40000002

@@ -1112,7 +1112,8 @@ int gsyeig_workspace_size(int64_t n, int64_t s, const gsyeig_opts *opts, size_t 
     if (o.reorth == 2)  // omega estimates; Gram matrix of the basis and its diagonal-block inverses
         b += sizeof(double) * ((size_t)(3 * (mmax + 8) + 8) + (size_t)mmax * (size_t)mmax +
                                (size_t)cdiv(mmax, NB) * NB * NB);
-    if (o.variant == GSYEIG_KE) b += 2 * sizeof(double) * (size_t)ldv * (size_t)n;  // C and its scratch
+    if (o.variant != GSYEIG_KI) b += 2 * sizeof(double) * (size_t)ldv * (size_t)n;  // C and its scratch
+    if (o.variant == GSYEIG_TD) b += syev_small_scratch(n, s) + sizeof(double) * (size_t)(n + 1) * (size_t)s;
     if (o.invert) {
         b += sizeof(double) * (size_t)ldv * (size_t)s;                // inverse-pencil vectors
         if (o.prec == GSYEIG_FP64) b += sizeof(double) * (size_t)ldv * (size_t)n;  // copy of A
@@ -1364,8 +1365,8 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     if (!o.invert) ctx->n_fallback = ctx->fallback_why = 0;
     if ((o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) || o.block < 1 || (o.invert != 0 && o.invert != 1) ||
         o.reorth < 0 || o.reorth > 2 ||
-        (o.which != 0 && o.which != 1) || (o.variant != GSYEIG_KI && o.variant != GSYEIG_KE) ||
-        (o.variant == GSYEIG_KE && (o.prec != GSYEIG_FP64 || o.block != 1)))
+        (o.which != 0 && o.which != 1) || o.variant < GSYEIG_KI || o.variant > GSYEIG_TD ||
+        (o.variant != GSYEIG_KI && (o.prec != GSYEIG_FP64 || o.block != 1 || o.invert)))
         return -8;
     if (o.block > 1) TRY(blz_check_dims(n, s, o.prec == GSYEIG_MIXED ? mixed_block(n, s, &o) : s, &o));
     if (!Lambda) return -9;
@@ -1408,12 +1409,13 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
     LzResult r{};
     BlzResult br{};
     LzOp lop = op_fp64(A, lda, B, ldb, Dinv);
-    if (o.variant == GSYEIG_KE) {
-        // GS2: C = U^-T A U^-1 with the block solves of the factor
+    if (o.variant == GSYEIG_KE || o.variant == GSYEIG_TD) {
+        // GS2: C = U^-T A U^-1 with the block solves of the factor (TD keeps
+        // C at leading dimension n, the dense eigensolver's layout)
         const double *sb;
         TRY(block_sb_fp64(ctx, n, B, ldb, Dinv, &sb));
         const double *Wd = (ctx->trsv_block == 64) ? nullptr : (const double *)ctx->ws[WS_W];
-        const int64_t ldc = round_ld(n);
+        const int64_t ldc = (o.variant == GSYEIG_TD) ? n : round_ld(n);
         void *pc, *pt;
         TRY(ws_get(ctx, WS_CKE, sizeof(double) * (size_t)ldc * (size_t)n, &pc));
         TRY(ws_get(ctx, WS_CKE2, sizeof(double) * (size_t)ldc * (size_t)n, &pt));
@@ -1432,6 +1434,25 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
         r.nconv = br.nconv;
         r.t_loop_ms = br.t_loop_ms;
         r.t_ritz_ms = br.t_ritz_ms;
+    } else if (o.variant == GSYEIG_TD) {
+        // TD1-TD3 (Sec. 2.2): Householder reduction of C to tridiagonal form,
+        // the s wanted eigenpairs of the tridiagonal matrix (bisection,
+        // inverse iteration), back-transformation by the reflectors
+        void *p;
+        TRY(ws_get(ctx, WS_TRI, syev_small_scratch(n, s), &p));
+        double *scr = (double *)p;
+        TRY(ws_get(ctx, WS_Y2, sizeof(double) * ((size_t)n * (size_t)s + (size_t)s + 8), &p));
+        double *Q = (double *)p, *w = Q + n * s;
+        HIP_TRY(hipEventRecord(ctx->ev[6], ctx->stream));
+        ctx->syev_site = 4;
+        TRY(syev_dense(ctx, n, lop.C ? const_cast<double *>(lop.C) : nullptr, s, o.which, w, Q, scr, ctx->stream));
+        TRY(launch_copy(w, Lambda, s, ctx->stream));
+        TRY(launch_blk_copy(Q, n, X, ldx, n, s, ctx->stream));
+        HIP_TRY(hipEventRecord(ctx->ev[7], ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        HIP_TRY(hipEventElapsedTime(&r.t_loop_ms, ctx->ev[6], ctx->ev[7]));
+        r.steps = 0;
+        r.nconv = s;
     } else {
         const int lrc = lz_solve(ctx, n, s, s, lop, &o, Lambda, X, ldx, &r);
         if (lrc && lrc != GSYEIG_ENOCONV) return lrc;  // ENOCONV: finish, report in info

@@ -281,6 +281,9 @@ int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, 
 // overlapped by more than 0.5 (two device ints)
 int orthonormalise_cols(gsyeig_ctx *ctx, int64_t m, int64_t nw, double *S, int64_t lds, int *info_d);
 int64_t syev_small_max();
+// syev_small without its order limit (the n x n C of variant TD)
+int syev_dense(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
+               double *scratch, hipStream_t st, double floor_rel = 0.0, double floor_shift = 0.0);
 
 // block Lanczos with thick restart (blz.hip)
 struct BlkOp {             // C = U^-T A U^-1 on blocks (TRSM, SYMM on the matrix cores)

@@ -744,6 +744,15 @@ int syev_small(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, 
                double *scratch, hipStream_t st, double floor_rel, double floor_shift)
 {
     if (N < 1 || N > SYTRD_MAX || nwant < 1 || nwant > N) return GSYEIG_EHIP;
+    return syev_dense(ctx, N, H, nwant, which, w, Q, scratch, st, floor_rel, floor_shift);
+}
+
+// The same for any order N (variant TD's n x n C): the reduction is the
+// whole-GPU one above 192, every index product 64-bit.
+int syev_dense(gsyeig_ctx *ctx, int64_t N, double *H, int64_t nwant, int which, double *w, double *Q,
+               double *scratch, hipStream_t st, double floor_rel, double floor_shift)
+{
+    if (N < 1 || N > INT32_MAX / 2 || nwant < 1 || nwant > N) return GSYEIG_EHIP;
     double *d = scratch, *e = d + N, *tau = e + N, *tri = tau + N + 8;
     double *aux = tri + 7 * N * nwant;
     if (sytrd_launch(N, H, d, e, tau, aux, st)) return GSYEIG_EHIP;

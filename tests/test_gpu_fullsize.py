@@ -1,6 +1,6 @@
 """Parity at the full benchmark size (n = 16384, s = 100, FP64), in the launch
-configuration the bench times, for variant KI (the headline) and variant KE
-(explicit C).  The oracle cannot solve this size, so it
+configuration the bench times, for variant KI (the headline), variant KE
+(explicit C) and the dense comparator TD.  The oracle cannot solve this size, so it
 checks what it can compute one by one: every eigenvalue against the
 generator's exact spectrum, and sampled pairs (x_i, lambda_i) through the
 oracle's own matrix-vector products (residual) and back-substitution
@@ -20,7 +20,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("variant", ["KI", "KE"])
+@pytest.mark.parametrize("variant", ["KI", "KE", "TD"])
 def test_full_size_known_spectrum(orc, variant):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
@@ -34,7 +34,7 @@ def test_full_size_known_spectrum(orc, variant):
     B_h = B.cpu().numpy()
     say("fullsize-solve", n, s, variant)
     o = gs.gsyeig_opts_default()
-    o.variant = gs.GSYEIG_KE if variant == "KE" else gs.GSYEIG_KI
+    o.variant = {"KI": gs.GSYEIG_KI, "KE": gs.GSYEIG_KE, "TD": gs.GSYEIG_TD}[variant]
     with gs.Solver() as sv:
         lam, X, info = sv.solve(A, B, s, opts=o)
     torch.cuda.synchronize()

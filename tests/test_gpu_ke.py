@@ -1,8 +1,9 @@
-"""Variant KE (Section 2.3; Table 1 keys GS2 and KE) through the C ABI:
-the explicit C = U^-T A U^-1 against the oracle's or_form_c element by
-element and against the generator's exact C = Y diag(lam) Y^T; the KE solve
-(one symmetric product per Lanczos step) against the oracle's solve and
-against the KI solve of the same pencil."""
+"""Variants KE (Section 2.3; Table 1 keys GS2 and KE) and TD (Section 2.2;
+keys TD1-TD3) through the C ABI: the explicit C = U^-T A U^-1 against the
+oracle's or_form_c element by element and against the generator's exact
+C = Y diag(lam) Y^T; the KE solve (one symmetric product per Lanczos step)
+and the TD solve (Householder tridiagonalisation of C) against the oracle's
+solve and against the KI solve of the same pencil."""
 import sys
 
 import numpy as np
@@ -120,10 +121,55 @@ def test_ke_rejects_unsupported_modes(gs, ctx, torch):
     d = gen.known_spectrum(n, seed=204)
     Lam = torch.zeros(2, dtype=torch.float64, device="cuda")
     X = torch.zeros(2, n, dtype=torch.float64, device="cuda")
-    for kw in (dict(prec=gs.GSYEIG_MIXED), dict(block=16), dict(variant=2)):
+    for kw in (dict(prec=gs.GSYEIG_MIXED), dict(block=16), dict(variant=3), dict(invert=1),
+               dict(variant=gs.GSYEIG_TD, prec=gs.GSYEIG_MIXED)):
         o = gs.gsyeig_opts_default()
         o.variant = gs.GSYEIG_KE
         for k, v in kw.items():
             setattr(o, k, v)
         rc, _ = gs.gsyeig_solve(ctx, n, 2, dev(torch, d["A"]), n, dev(torch, d["B"]), n, o, Lam, X, n)
         assert rc == -8, kw
+
+
+@pytest.mark.parametrize("n,s,law,which", [(2, 1, "spaced", 0), (65, 5, "spaced", 0), (700, 35, "clustered", 0),
+                                           (1500, 75, "spaced", 1), (1537, 20, "spaced", 0)])
+def test_td_solve_matches_oracle(gs, ctx, torch, orc, n, s, law, which):
+    say("td solve", n, s, law, which)
+    d = gen.known_spectrum(n, law, seed=gen.BASE_SEED, stream=(205, n, which))
+    o = gs.gsyeig_opts_default()
+    o.variant = gs.GSYEIG_TD
+    o.which = which
+    Lam = torch.zeros(s, dtype=torch.float64, device="cuda")
+    X = torch.zeros(s, n, dtype=torch.float64, device="cuda")
+    rc, info = gs.gsyeig_solve(ctx, n, s, dev(torch, d["A"]), n, dev(torch, d["B"]), n, o, Lam, X, n)
+    assert rc == 0, info.as_dict()
+    assert info.steps == 0 and info.converged == s
+    lam, Xh = host(Lam), host(X)
+    lam_o, X_o = orc.gsyeig(d["A"], d["B"], s, which="largest" if which else "smallest")
+    mx = np.max(np.abs(d["lam"]))
+    assert np.max(np.abs(lam - lam_o)) <= 1e-12 * mx
+    lam_true = np.sort(d["lam"])
+    lam_true = lam_true[:s] if which == 0 else lam_true[n - s:]
+    assert np.max(np.abs(lam - lam_true)) <= 1e-12 * mx
+    m = orc.metrics(d["A"], d["B"], lam, Xh)
+    assert m["eta_max"] <= 1e-12 and m["omega"] <= 1e-10
+    assert info.eta_max <= 1e-12
+    if law == "spaced" and which == 0 and s <= 10:
+        assert np.max(np.abs(Xh - X_o)) <= 1e-9 * np.max(np.abs(X_o))
+
+
+def test_td_ke_ki_agree(gs, ctx, torch):
+    n, s = 3000, 40
+    d = gen.known_spectrum(n, "spaced", seed=gen.BASE_SEED, stream=(206,))
+    A = dev(torch, d["A"])
+    lams = []
+    for var in (gs.GSYEIG_KI, gs.GSYEIG_KE, gs.GSYEIG_TD):
+        say("td/ke/ki", var)
+        o = gs.gsyeig_opts_default()
+        o.variant = var
+        with gs.Solver() as sv:
+            lam, X, info = sv.solve(A, dev(torch, d["B"]), s, o)
+        assert info["rc"] == 0 and info["eta_max"] <= 1e-12
+        lams.append(host(lam))
+    assert np.max(np.abs(lams[0] - lams[2])) <= 1e-12
+    assert np.max(np.abs(lams[1] - lams[2])) <= 1e-12
