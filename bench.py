@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--variant", choices=["ki", "ke"], default="ki",
                     help="configs 0/1: the timed variant (KI: implicit operator, the default; KE: explicit C)")
     ap.add_argument("--no-ke", action="store_true", help="configs 0/1: skip the KE solve timed beside KI")
+    ap.add_argument("--trsv-sweep", type=int, default=-1,
+                    help="super-block sweep kernels (gsyeig_set_trsv_sweep): 0 work queue, 1 one workgroup per tile")
     ap.add_argument("--sweep-s", default="",
                     help="comma-separated s values: time the variants (--sweep-variants) against s on the config's "
                          "input (the shape of the paper's Figs. 1-2); one JSON line per point, no headline line")
@@ -158,6 +160,10 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     solver = gs.Solver()
+    if args.trsv_sweep >= 0:
+        rc = gs.gsyeig_set_trsv_sweep(solver.ctx, args.trsv_sweep)
+        if rc:
+            raise gs.GsyeigError("gsyeig_set_trsv_sweep", rc)
     opts = gs.gsyeig_opts_default()
     opts.profile_every = args.profile_every
     if args.reorth >= 0:
@@ -363,6 +369,8 @@ def trsv_only(args, cfg):
     x = torch.empty_like(b)
     C = torch.empty_like(U)
     with gs.Solver() as sv:
+        if args.trsv_sweep >= 0:
+            gs.gsyeig_set_trsv_sweep(sv.ctx, args.trsv_sweep)
         for trans in (0, 1):
             for _ in range(max(1, args.steps)):
                 if lp:

@@ -203,10 +203,22 @@ int gsyeig_destroy(gsyeig_ctx *ctx);
  * Host-only setting; takes effect at the next factorisation or solve. */
 int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
 
+/* Kernel design of the 512-row super-block sweeps (KI1/KI3) on this
+ * context: 0 (default) = work-queue sweeps -- the panel products with
+ * already-solved super-blocks are separate queue items taken in the order
+ * the chain needs them, so the links wait only on their neighbours' values
+ * (k_trsv_q.hip); 1 = one persistent workgroup per 64-row tile that streams
+ * its whole panel as the values arrive (k_trsv_w.hip).  Both compute the
+ * same solve with the same operation order per output up to the grouping
+ * of the panel sums.  Host-only setting; returns 0, -1 (NULL ctx) or -2. */
+int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind);
+
 /* Bound on the polls of each wait in the chained (persistent) triangular
  * sweeps of KI1/KI3 on this context: 0 restores the built-in bound (2^22
- * polls); the bound is consulted from the 33rd poll of a wait on, so values
- * below 32 act as 32.  A wait that runs out stores 0.0 for the awaited value, marks the
+ * polls).  The work-queue sweeps read the bound once per workgroup; the
+ * per-tile and 64-row sweeps consult it from the 33rd poll of a wait on, so
+ * there values below 32 act as 32.  A wait that runs out stores 0.0 for the
+ * awaited value, marks the
  * context's wait record and lets the kernel finish, so no wait can hang the
  * GPU; the call reports GSYEIG_ESPIN.  Meant for tests of that error path
  * (a tiny bound forces expiries in a healthy run).  Synchronises; returns

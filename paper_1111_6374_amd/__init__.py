@@ -33,7 +33,7 @@ EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_symv_noalloc", "gsyeig_apply_op", "gsyeig_form_c",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
-    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_sync", "gsyeig_solve_batched",
+    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_set_trsv_sweep", "gsyeig_sync", "gsyeig_solve_batched",
     "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_apply_op_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
 )
 
@@ -102,6 +102,7 @@ def lib():
             "gsyeig_destroy": ([P], I),
             "gsyeig_set_trsv_block": ([P, I64], I),
             "gsyeig_set_spin_limit": ([P, ctypes.c_uint], I),
+            "gsyeig_set_trsv_sweep": ([P, I], I),
             "gsyeig_sync": ([P], I),
             "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
             "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
@@ -173,6 +174,10 @@ def gsyeig_destroy(ctx) -> int:
 
 def gsyeig_set_trsv_block(ctx, rows) -> int:
     return lib().gsyeig_set_trsv_block(ctx, rows)
+
+
+def gsyeig_set_trsv_sweep(ctx, kind) -> int:
+    return lib().gsyeig_set_trsv_sweep(ctx, kind)
 
 
 def gsyeig_set_spin_limit(ctx, limit) -> int:

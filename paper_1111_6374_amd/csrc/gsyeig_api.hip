@@ -92,7 +92,9 @@ static int ctl_check(gsyeig_ctx *ctx)
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (h[0] || h[1]) {
-        // a wait expired: restart both control blocks from a clean state
+        // a wait expired: restart both control blocks and the queue sweeps'
+        // partial buffers from a clean state
+        ctx->trsvq_n = -1;
         int rc;
         if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)))
             return rc;
@@ -188,6 +190,39 @@ static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu,
     return prepare_solves(ctx, n, U, ldu, *Dinv);
 }
 
+// The super-block sweeps on U = D (I + W) (W FP64 or FP32): the work-queue
+// kernels (default) or one workgroup per tile (gsyeig_set_trsv_sweep).
+// KI3 takes b, or (b == nullptr) the SYMV tile partials Pr / Pc.
+static int sweep_n(gsyeig_ctx *ctx, int64_t n, const void *W, int w_f32, int64_t ldw, const double *sb,
+                   const double *b, double *x)
+{
+    if (ctx->trsv_sweep == 0) {
+        TrsvQ q;
+        TRY(trsvq_prepare(ctx, n, &q));
+        return w_f32 ? launch_trsvq_n_f32((const float *)W, ldw, n, sb, b, x, ctx->ctl_n, q, ctx->stream)
+                     : launch_trsvq_n((const double *)W, ldw, n, sb, b, x, ctx->ctl_n, q, ctx->stream);
+    }
+    return w_f32 ? launch_trsv_w_n_f32((const float *)W, ldw, n, sb, b, x, ctx->ctl_n, ctx->stream)
+                 : launch_trsv_w_n((const double *)W, ldw, n, sb, b, x, ctx->ctl_n, ctx->stream);
+}
+
+static int sweep_t(gsyeig_ctx *ctx, int64_t n, const void *W, int w_f32, int64_t ldw, const double *sb,
+                   const double *b, const double *Pr, const double *Pc, int maxch, int ch, double *x)
+{
+    if (ctx->trsv_sweep == 0) {
+        TrsvQ q;
+        TRY(trsvq_prepare(ctx, n, &q));
+        return w_f32 ? launch_trsvq_t_f32((const float *)W, ldw, n, sb, b, Pr, Pc, maxch, ch, x, ctx->ctl_t, q,
+                                          ctx->stream)
+                     : launch_trsvq_t((const double *)W, ldw, n, sb, b, Pr, Pc, maxch, ch, x, ctx->ctl_t, q,
+                                      ctx->stream);
+    }
+    if (b) return w_f32 ? launch_trsv_w_t_f32((const float *)W, ldw, n, sb, b, x, ctx->ctl_t, ctx->stream)
+                        : launch_trsv_w_t((const double *)W, ldw, n, sb, b, x, ctx->ctl_t, ctx->stream);
+    return w_f32 ? launch_trsv_w_t_rows_f32((const float *)W, ldw, n, sb, Pr, Pc, maxch, ch, x, ctx->ctl_t, ctx->stream)
+                 : launch_trsv_w_t_rows((const double *)W, ldw, n, sb, Pr, Pc, maxch, ch, x, ctx->ctl_t, ctx->stream);
+}
+
 static int solve_n(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
                    const double *b, double *x)
 {
@@ -199,8 +234,7 @@ static int solve_n(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, con
         TRY(launch_copy(b, (double *)p, n, ctx->stream));
         b = (const double *)p;
     }
-    return launch_trsv_w_n((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], b, x,
-                           ctx->ctl_n, ctx->stream);
+    return sweep_n(ctx, n, ctx->ws[WS_W], 0, round_ld(n), (const double *)ctx->ws[WS_SB], b, x);
 }
 
 static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, const double *Dinv,
@@ -208,8 +242,8 @@ static int solve_t(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu, con
 {
     if (ctx->trsv_block == 64)
         return launch_trsv_t(U, ldu, n, Dinv, aux_m(Dinv, n), b, x, ctx->ctl_t, ctx->stream);
-    return launch_trsv_w_t((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB], b, x,
-                           ctx->ctl_t, ctx->stream);
+    return sweep_t(ctx, n, ctx->ws[WS_W], 0, round_ld(n), (const double *)ctx->ws[WS_SB], b, nullptr, nullptr, 0, 0,
+                   x);
 }
 
 // Super-block inverses of an FP64 factor for the block solves: built with
@@ -281,7 +315,7 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
         return 0;
     }
     if (op.f32)
-        TRY(launch_trsv_w_n_f32(op.W32, op.ldw32, n, op.sb, w, tmp, ctx->ctl_n, ctx->stream));
+        TRY(sweep_n(ctx, n, op.W32, 1, op.ldw32, op.sb, w, tmp));
     else
         TRY(solve_n(ctx, n, op.U, op.ldu, op.Dinv, w, tmp));
     if (sample) HIP_TRY(hipEventRecord(e[1], ctx->stream));
@@ -296,10 +330,10 @@ static int apply_op(gsyeig_ctx *ctx, int64_t n, const LzOp &op, const double *w,
             TRY(launch_symv_partials(ctx, n, op.A, op.lda, tmp, &Pr, &Pc, &maxch, &ch));
         if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
         if (op.f32)
-            TRY(launch_trsv_w_t_rows_f32(op.W32, op.ldw32, n, op.sb, Pr, Pc, maxch, ch, z, ctx->ctl_t, ctx->stream));
+            TRY(sweep_t(ctx, n, op.W32, 1, op.ldw32, op.sb, nullptr, Pr, Pc, maxch, ch, z));
         else
-            TRY(launch_trsv_w_t_rows((const double *)ctx->ws[WS_W], round_ld(n), n, (const double *)ctx->ws[WS_SB],
-                                     Pr, Pc, maxch, ch, z, ctx->ctl_t, ctx->stream));
+            TRY(sweep_t(ctx, n, ctx->ws[WS_W], 0, round_ld(n), (const double *)ctx->ws[WS_SB], nullptr, Pr, Pc, maxch,
+                        ch, z));
     } else {
         TRY(launch_symv(ctx, n, op.A, op.lda, tmp, z));
         if (sample) HIP_TRY(hipEventRecord(e[2], ctx->stream));
@@ -1019,6 +1053,8 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
     ctx->stream = (hipStream_t)hip_stream;
     ctx->symv_map_n = -1;
     ctx->trsv_block = 512;
+    ctx->trsv_sweep = 0;
+    ctx->trsvq_n = -1;
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     if (hipHostMalloc(&ctx->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
@@ -1064,6 +1100,14 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
     if (!ctx) return -1;
     if (rows != 64 && rows != trsv_sb_rows()) return -2;
     ctx->trsv_block = rows;
+    return 0;
+}
+
+int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind)
+{
+    if (!ctx) return -1;
+    if (kind != 0 && kind != 1) return -2;
+    ctx->trsv_sweep = kind;
     return 0;
 }
 
@@ -1520,10 +1564,16 @@ int gsyeig_trsv_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
     TRY(launch_diag_inv_f32(U, ldu, n, Dinv, ctx->stream));
     TRY(launch_make_w_f32(U, ldu, n, Dinv, sb, W32, ldw, ctx->stream));
     TRY(ctl_clear_err(ctx));
-    if (trans == 0)
-        TRY(launch_trsv_w_n_f32(W32, ldw, n, sb, b, x, ctx->ctl_n, ctx->stream));
-    else
-        TRY(launch_trsv_w_t_f32(W32, ldw, n, sb, b, x, ctx->ctl_t, ctx->stream));
+    if (trans == 0) {
+        if (b == x) {  // the diagonal part reads b across its super-block: solve from a copy
+            TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)n, &p));
+            TRY(launch_copy(b, (double *)p, n, ctx->stream));
+            b = (const double *)p;
+        }
+        TRY(sweep_n(ctx, n, W32, 1, ldw, sb, b, x));
+    } else {
+        TRY(sweep_t(ctx, n, W32, 1, ldw, sb, b, nullptr, nullptr, 0, 0, x));
+    }
     return ctl_check(ctx);
 }
 

@@ -65,6 +65,7 @@ enum WsSlot {
     WS_BLZ,        // block Lanczos: projected matrix, Ritz coefficients, blocks, kept Ritz vectors
     WS_PRO,        // omega estimates of the partial re-orthogonalisation (3 x (max_steps + 2))
     WS_PROG,       // Gram matrix V_m^T V_m of the semi-orthogonal basis and its Cholesky data
+    WS_TRSVQ,      // work queues and sentinel partial buffers of the queue sweeps
     WS_CKE,        // variant KE: the explicit C = U^-T A U^-1 (n x n FP64)
     WS_CKE2,       // variant KE: the second n x n buffer of its formation
     WS_COUNT
@@ -79,6 +80,10 @@ struct gsyeig_ctx {
     PCtl *ctl_t;
     int64_t ctl_rows;   // staging capacity (rows) of each staging vector
     int64_t trsv_block; // 64: chained 64-row solves; 512: super-block solves
+    int trsv_sweep;     // super-block solves: 0 = work-queue sweeps, 1 = one workgroup per tile
+    int64_t trsvq_n;    // n for which WS_TRSVQ holds the queues (-1: none)
+    int trsvq_nitems_n, trsvq_nitems_t;
+    size_t trsvq_pbytes;  // byte offset of the partial buffers in WS_TRSVQ
     int64_t symv_map_n; // n for which WS_SYMVMAP is valid
     int64_t symv_items;
     unsigned spin_limit;  // polls per wait of the chained kernels (0 = SPIN_LIMIT)
@@ -175,6 +180,23 @@ int launch_trsv_w_t_rows_f32(const float *W, int64_t ldw, int64_t n, const doubl
                              const double *Pc, int maxch, int ch, double *x, PCtl *ctl, hipStream_t st);
 int launch_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows, int64_t cols,
                   hipStream_t st);
+// work-queue sweeps on U = D (I + W) (k_trsv_q.hip); b == nullptr in KI3:
+// the right-hand side is the SYMV tile partials Pr / Pc
+struct TrsvQ {
+    const int2 *items_n; int nitems_n;
+    const int2 *items_t; int nitems_t;
+    double *P, *Q;         // sentinel-initialised partials, nblk x nsb x 64 each
+    int nsb;
+};
+int trsvq_prepare(gsyeig_ctx *ctx, int64_t n, TrsvQ *q);
+int launch_trsvq_n(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x, PCtl *ctl,
+                   const TrsvQ &q, hipStream_t st);
+int launch_trsvq_n_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, double *x,
+                       PCtl *ctl, const TrsvQ &q, hipStream_t st);
+int launch_trsvq_t(const double *W, int64_t ldw, int64_t n, const double *sbw, const double *b, const double *Pr,
+                   const double *Pc, int maxch, int ch, double *x, PCtl *ctl, const TrsvQ &q, hipStream_t st);
+int launch_trsvq_t_f32(const float *W, int64_t ldw, int64_t n, const double *sbw, const double *b, const double *Pr,
+                       const double *Pc, int maxch, int ch, double *x, PCtl *ctl, const TrsvQ &q, hipStream_t st);
 // M holds [M_i | M'_i] for all blocks (see launch_make_m)
 int launch_make_m(const double *U, int64_t ldu, int64_t n, const double *Dinv, double *M,
                   hipStream_t st);
