@@ -180,6 +180,23 @@ typedef struct {
                            /*   and steps is 0                                  */
 } gsyeig_info;
 
+/* Choices made by gsyeig_autotune. */
+typedef struct {
+    int64_t n_bucket;      /* the power of two >= n (1024..65536) the entry covers */
+    int prec;              /* GSYEIG_FP64 or GSYEIG_MIXED (FP32 storage of A, U)   */
+    int trsv_block;        /* 64 or 512 (gsyeig_set_trsv_block)                    */
+    int trsv_sweep;        /* 0 or 1 (gsyeig_set_trsv_sweep)                        */
+    int from_cache;        /* 1: taken from the cache file, nothing was measured    */
+    int64_t gemm_big_min;  /* matrix-core products use 128x128 tiles when both     */
+                           /*   output edges are >= this (0: 64x64 tiles only)     */
+    double op_ms;          /* measured operator application (KI1-KI3) of the choice */
+    double gemm_ms;        /* measured n x n x 256 product of the choice            */
+    double op_ms_cand[3];  /* operator with (512, queue), (512, per tile), (64)     */
+                           /*   sweeps (FP32 storage: the 64-row chain is not used, */
+                           /*   entry 2 is 0)                                       */
+    double gemm_ms_cand[2];/* product with 128x128 tiles allowed, and without       */
+} gsyeig_tuning;
+
 /* Library version string (host, static storage). */
 const char *gsyeig_version(void);
 
@@ -212,6 +229,23 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
  * same solve with the same operation order per output up to the grouping
  * of the panel sums.  Host-only setting; returns 0, -1 (NULL ctx) or -2. */
 int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind);
+
+/* Project-written autotuner: picks the kernel variants of this library for
+ * order n and precision `prec` by timing them on synthetic operands of the
+ * same shape on the current device -- the triangular sweeps' super-block
+ * size and kernel design (the implicit operator KI1-KI3 timed as a whole,
+ * FP64 or FP32 storage) and the matrix-core product tile (64x64 or 128x128,
+ * an n x n x 256 product, FP64 or FP32 compute) -- and applies them: the
+ * sweep choice to ctx, the tile choice process-wide.  Measurements run at
+ * min(n_bucket, 32768) (n_bucket = the power of two >= n, 1024..65536);
+ * they allocate and free about 2 n^2 doubles of device memory.
+ * cache_path (host string, may be NULL): a JSON file keyed by (device
+ * architecture, prec, n_bucket); an entry found there is applied without
+ * measuring, a new measurement is added to it.  *out (host, may be NULL)
+ * receives the choices.  Synchronises.  Returns 0, -1 (NULL ctx), -2
+ * (n < 1), -3 (prec), GSYEIG_ENOMEM, GSYEIG_EHIP (also for an unwritable
+ * cache file, after applying the measured choices). */
+int gsyeig_autotune(gsyeig_ctx *ctx, int64_t n, int prec, const char *cache_path, gsyeig_tuning *out);
 
 /* Bound on the polls of each wait in the chained (persistent) triangular
  * sweeps of KI1/KI3 on this context: 0 restores the built-in bound (2^22

@@ -33,7 +33,7 @@ EXPORTS = (
     "gsyeig_version", "gsyeig_opts_default", "gsyeig_create", "gsyeig_destroy",
     "gsyeig_workspace_size", "gsyeig_potrf", "gsyeig_trsv", "gsyeig_symv", "gsyeig_symv_noalloc", "gsyeig_apply_op", "gsyeig_form_c",
     "gsyeig_lanczos_run", "gsyeig_tridiag_eig", "gsyeig_lanczos", "gsyeig_backsolve",
-    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_set_trsv_sweep", "gsyeig_sync", "gsyeig_solve_batched",
+    "gsyeig_check", "gsyeig_solve", "gsyeig_set_trsv_block", "gsyeig_set_spin_limit", "gsyeig_set_trsv_sweep", "gsyeig_autotune", "gsyeig_sync", "gsyeig_solve_batched",
     "gsyeig_trsv_lp", "gsyeig_symv_lp", "gsyeig_apply_op_lp", "gsyeig_trsm_lp", "gsyeig_syev_small", "gsyeig_refine",
 )
 
@@ -84,6 +84,19 @@ class gsyeig_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class gsyeig_tuning(ctypes.Structure):
+    _fields_ = [("n_bucket", ctypes.c_int64), ("prec", ctypes.c_int), ("trsv_block", ctypes.c_int),
+                ("trsv_sweep", ctypes.c_int), ("from_cache", ctypes.c_int), ("gemm_big_min", ctypes.c_int64),
+                ("op_ms", ctypes.c_double), ("gemm_ms", ctypes.c_double), ("op_ms_cand", ctypes.c_double * 3),
+                ("gemm_ms_cand", ctypes.c_double * 2)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["op_ms_cand"] = list(self.op_ms_cand)
+        d["gemm_ms_cand"] = list(self.gemm_ms_cand)
+        return d
+
+
 _lib = None
 
 
@@ -103,6 +116,7 @@ def lib():
             "gsyeig_set_trsv_block": ([P, I64], I),
             "gsyeig_set_spin_limit": ([P, ctypes.c_uint], I),
             "gsyeig_set_trsv_sweep": ([P, I], I),
+            "gsyeig_autotune": ([P, I64, I, ctypes.c_char_p, ctypes.POINTER(gsyeig_tuning)], I),
             "gsyeig_sync": ([P], I),
             "gsyeig_workspace_size": ([I64, I64, ctypes.POINTER(gsyeig_opts), ctypes.POINTER(ctypes.c_size_t)], I),
             "gsyeig_potrf": ([P, I64, P, I64, ctypes.POINTER(gsyeig_opts), P], I),
@@ -178,6 +192,13 @@ def gsyeig_set_trsv_block(ctx, rows) -> int:
 
 def gsyeig_set_trsv_sweep(ctx, kind) -> int:
     return lib().gsyeig_set_trsv_sweep(ctx, kind)
+
+
+def gsyeig_autotune(ctx, n, prec=GSYEIG_FP64, cache_path=None):
+    """Returns (rc, gsyeig_tuning)."""
+    t = gsyeig_tuning()
+    rc = lib().gsyeig_autotune(ctx, n, prec, cache_path.encode() if cache_path else None, ctypes.byref(t))
+    return rc, t
 
 
 def gsyeig_set_spin_limit(ctx, limit) -> int:

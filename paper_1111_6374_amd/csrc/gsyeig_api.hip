@@ -1103,6 +1103,159 @@ int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows)
     return 0;
 }
 
+}  // extern "C"
+
+// time `reps` applications of f after `warm` untimed ones (ms per call)
+template <typename F>
+static int time_calls(gsyeig_ctx *ctx, int warm, int reps, F f, double *ms)
+{
+    for (int k = 0; k < warm; ++k) TRY(f());
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    for (int k = 0; k < reps; ++k) TRY(f());
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIP_TRY(hipEventSynchronize(ctx->ev[1]));
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+    *ms = t / reps;
+    return 0;
+}
+
+static int autotune_measure(gsyeig_ctx *ctx, int64_t nm, int prec, double *U, double *A, int64_t ld, double *w,
+                            double *z, double *Cb, gsyeig_tuning *t)
+{
+    TRY(launch_synth_operands(U, A, ld, nm, 0x6374ull + (uint64_t)nm, ctx->stream));
+    TRY(launch_fill_splitmix(w, nm, 17, ctx->stream));
+    TRY(ctl_reserve(ctx, nm));
+    void *p;
+    TRY(ws_get(ctx, WS_TMP2, sizeof(double) * (size_t)nm, &p));
+    double *tmp = (double *)p;
+    const int64_t save_block = ctx->trsv_block;
+    const int save_sweep = ctx->trsv_sweep;
+    struct Cand { int block, sweep; } cands[3] = {{512, 0}, {512, 1}, {64, 0}};
+    float *U32 = nullptr;
+    if (prec == GSYEIG_MIXED) {
+        TRY(ws_get(ctx, WS_U32, sizeof(float) * (size_t)ld * (size_t)nm, &p));
+        U32 = (float *)p;
+        TRY(launch_to_f32(U, ld, U32, ld, nm, nm, ctx->stream));
+    }
+    double best = 1e300;
+    for (int c = 0; c < 3; ++c) {
+        t->op_ms_cand[c] = 0.0;
+        if (prec == GSYEIG_MIXED && cands[c].block == 64) continue;  // FP32 storage: super-block sweeps only
+        ctx->trsv_block = cands[c].block;
+        ctx->trsv_sweep = cands[c].sweep;
+        LzOp op;
+        if (prec == GSYEIG_MIXED) {
+            TRY(mixed_operator(ctx, nm, A, ld, U32, ld, false, &op));
+        } else {
+            double *Dinv;
+            TRY(dinv_from_u(ctx, nm, U, ld, &Dinv));
+            op = op_fp64(A, ld, U, ld, Dinv);
+        }
+        double ms;
+        TRY(time_calls(ctx, 2, 5, [&]() { return apply_op(ctx, nm, op, w, z, tmp); }, &ms));
+        t->op_ms_cand[c] = ms;
+        if (ms < best) {
+            best = ms;
+            t->trsv_block = cands[c].block;
+            t->trsv_sweep = cands[c].sweep;
+            t->op_ms = ms;
+        }
+    }
+    ctx->trsv_block = save_block;
+    ctx->trsv_sweep = save_sweep;
+    // product tile: an n x n x 256 update (the shape of the Cholesky's
+    // trailing products and of the block solves of GS2), both tile rules
+    const int64_t nc = std::min<int64_t>(nm, 8192);
+    const int64_t save_big = gemm_big_min();
+    const int64_t rules[2] = {2048, 0};
+    double gbest = 1e300;
+    for (int r = 0; r < 2; ++r) {
+        gemm_set_big_min(rules[r]);
+        GemmDesc d{};
+        d.m = nc; d.n = nc; d.k = 256;
+        d.A = A; d.lda = ld; d.a_layout = 1;
+        d.B = U; d.ldb = ld; d.b_layout = 1;
+        d.C = Cb; d.ldc = nc; d.c_layout = 0;
+        d.alpha = 1.0; d.beta = 0.0;
+        d.f32 = (prec == GSYEIG_MIXED) ? 1 : 0;
+        double ms;
+        TRY(time_calls(ctx, 1, 3, [&]() { return launch_gemm(d, ctx->stream); }, &ms));
+        t->gemm_ms_cand[r] = ms;
+        if (ms < gbest) {
+            gbest = ms;
+            t->gemm_big_min = rules[r];
+            t->gemm_ms = ms;
+        }
+    }
+    gemm_set_big_min(save_big);
+    return 0;
+}
+
+extern "C" {
+
+int gsyeig_autotune(gsyeig_ctx *ctx, int64_t n, int prec, const char *cache_path, gsyeig_tuning *out)
+{
+    if (!ctx) return -1;
+    if (n < 1) return -2;
+    if (prec != GSYEIG_FP64 && prec != GSYEIG_MIXED) return -3;
+    int64_t nb = 1024;
+    while (nb < n && nb < 65536) nb *= 2;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+    const char *arch = prop.gcnArchName;
+    gsyeig_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.n_bucket = nb;
+    t.prec = prec;
+    std::vector<TuneEntry> ents;
+    std::string others;
+    if (cache_path) {
+        TRY(tune_cache_load(cache_path, arch, &ents, &others));
+        for (const TuneEntry &e : ents)
+            if (e.prec == prec && e.n_bucket == nb) {
+                t.trsv_block = e.trsv_block;
+                t.trsv_sweep = e.trsv_sweep;
+                t.gemm_big_min = e.gemm_big_min;
+                t.op_ms = e.op_ms;
+                t.gemm_ms = e.gemm_ms;
+                t.from_cache = 1;
+                ctx->trsv_block = t.trsv_block;
+                ctx->trsv_sweep = t.trsv_sweep;
+                gemm_set_big_min(t.gemm_big_min);
+                if (out) *out = t;
+                return 0;
+            }
+    }
+    const int64_t nm = std::min<int64_t>(nb, 32768), ld = round_ld(nm);
+    const int64_t nc = std::min<int64_t>(nm, 8192);
+    double *U = nullptr, *A = nullptr, *v = nullptr, *Cb = nullptr;
+    int rc = 0;
+    if (hipMalloc(&U, sizeof(double) * (size_t)ld * (size_t)nm) != hipSuccess ||
+        hipMalloc(&A, sizeof(double) * (size_t)ld * (size_t)nm) != hipSuccess ||
+        hipMalloc(&v, sizeof(double) * 2 * (size_t)ld) != hipSuccess ||
+        hipMalloc(&Cb, sizeof(double) * (size_t)nc * (size_t)nc) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = GSYEIG_ENOMEM;
+    }
+    if (!rc) rc = autotune_measure(ctx, nm, prec, U, A, ld, v, v + ld, Cb, &t);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (U) (void)hipFree(U);
+    if (A) (void)hipFree(A);
+    if (v) (void)hipFree(v);
+    if (Cb) (void)hipFree(Cb);
+    if (rc) return rc;
+    ctx->trsv_block = t.trsv_block;
+    ctx->trsv_sweep = t.trsv_sweep;
+    gemm_set_big_min(t.gemm_big_min);
+    if (out) *out = t;
+    if (cache_path) {
+        ents.push_back(TuneEntry{prec, nb, t.trsv_block, t.trsv_sweep, t.gemm_big_min, t.op_ms, t.gemm_ms});
+        return tune_cache_store(cache_path, arch, ents, others);
+    }
+    return 0;
+}
+
 int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind)
 {
     if (!ctx) return -1;

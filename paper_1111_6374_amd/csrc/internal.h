@@ -5,6 +5,9 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
+#include <vector>
+
 #include "../../include/gsyeig.h"
 
 // Block size of the triangular factor: diagonal blocks of U are NB x NB.
@@ -138,6 +141,23 @@ struct GemmDesc {
 int launch_gemm(const GemmDesc &d, hipStream_t st);
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st);
 int64_t gemm_splitk_parts(const GemmDesc &d);
+// process-wide tile choice of launch_gemm: 128x128 tiles when m and n are
+// both >= the given size (0: 64x64 tiles only); set by the autotuner
+void gemm_set_big_min(int64_t m);
+int64_t gemm_big_min();
+
+// autotuner (autotune.hip): the JSON cache and synthetic operands
+struct TuneEntry {
+    int prec;
+    int64_t n_bucket;
+    int trsv_block, trsv_sweep;
+    int64_t gemm_big_min;
+    double op_ms, gemm_ms;
+};
+int tune_cache_load(const char *path, const char *arch, std::vector<TuneEntry> *out, std::string *others);
+int tune_cache_store(const char *path, const char *arch, const std::vector<TuneEntry> &entries,
+                     const std::string &others);
+int launch_synth_operands(double *U, double *A, int64_t ld, int64_t n, uint64_t seed, hipStream_t st);
 
 int launch_diag_inv(const double *U, int64_t ldu, int64_t n, double *Dinv, hipStream_t st);
 // super-block solves (k_trsv_w.hip): Uinv_SS and its transpose per 512-row super-block

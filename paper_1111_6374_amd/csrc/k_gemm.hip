@@ -66,39 +66,54 @@ __device__ __forceinline__ int d_row(int lk, int r)
     else return 4 * lk + r;
 }
 
-template <typename TC, typename TA, typename TB, typename TCS, int AL, int BL>
+// WT = 1: 64x64 tiles, each wave a 32x32 quadrant (2x2 MFMA blocks);
+// WT = 2: 128x128 tiles, each wave a 64x64 quadrant (4x4 blocks, the
+// accumulators in the matrix cores' accumulation registers): twice the
+// products per LDS fragment and per byte staged, for large m and n.
+template <typename TC, typename TA, typename TB, typename TCS, int AL, int BL, int WT>
 __global__ __launch_bounds__(256) void k_gemm(Args g)
 {
     using V4 = typename Acc<TC>::type;
     constexpr int PAD = Acc<TC>::pad;
+    constexpr int TMX = TM * WT, TNX = TN * WT;   // tile
+    constexpr int NP = TMX * TK / 256;            // A (and B) values per thread per slab
     const TA *Ap = (const TA *)g.A;
     const TB *Bp = (const TB *)g.B;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t tm0 = (int64_t)blockIdx.x * TM;
-    const int64_t tn0 = (int64_t)blockIdx.y * TN;
-    if (g.upper_only && tm0 > tn0 + TN - 1) return;  // tile strictly below the diagonal
+    const int64_t tm0 = (int64_t)blockIdx.x * TMX;
+    const int64_t tn0 = (int64_t)blockIdx.y * TNX;
+    if (g.upper_only && tm0 > tn0 + TNX - 1) return;  // tile strictly below the diagonal
     const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
     const int64_t kend = (kbeg + g.kchunk < g.k) ? kbeg + g.kchunk : g.k;
 
-    __shared__ TC As[TK][TM + PAD];
-    __shared__ TC Bs[TK][TN + PAD];
+    __shared__ TC As[TK][TMX + PAD];
+    __shared__ TC Bs[TK][TNX + PAD];
 
     // The next slab is fetched while the current one is multiplied: loads
     // come from clamped in-bounds indices (no predicated load) and stay in
     // their storage type until stash, which converts them and zeroes the
     // out-of-range ones -- nothing waits for the loads before the products.
-    TA ra[4];
-    TB rb[4];
+    TA ra[NP];
+    TB rb[NP];
     unsigned am = 0, bm = 0;
+    // element p of this thread: A (AL = 0: contiguous rows) or B (BL = 1:
+    // contiguous columns) along the tile edge, else along K
+    auto a_idx = [&](int p, int &ii, int &kk) {
+        if constexpr (AL == 0) { ii = tid % TMX; kk = tid / TMX + (256 / TMX) * p; }
+        else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
+    };
+    auto b_idx = [&](int p, int &kk, int &jj) {
+        if constexpr (BL == 1) { jj = tid % TNX; kk = tid / TNX + (256 / TNX) * p; }
+        else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
+    };
     auto fetch = [&](int64_t k0) {
         am = bm = 0;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < NP; ++p) {
             int ii, kk;
-            if constexpr (AL == 0) { ii = tid & 63; kk = (tid >> 6) + 4 * p; }
-            else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
+            a_idx(p, ii, kk);
             const int64_t gi = tm0 + ii, gk = k0 + kk;
             const bool ok = gi < g.m && gk < kend;
             am |= (unsigned)ok << p;
@@ -109,10 +124,9 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
             }
         }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < NP; ++p) {
             int kk, jj;
-            if constexpr (BL == 1) { jj = tid & 63; kk = (tid >> 6) + 4 * p; }
-            else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
+            b_idx(p, kk, jj);
             const int64_t gk = k0 + kk, gj = tn0 + jj;
             bm |= (unsigned)(gk < kend && gj < g.n) << p;
             rb[p] = load_op<TB, BL>(Bp, g.ldb, gk < kend ? gk : kend - 1, gj < g.n ? gj : g.n - 1, nullptr);
@@ -120,27 +134,26 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < NP; ++p) {
             int ii, kk;
-            if constexpr (AL == 0) { ii = tid & 63; kk = (tid >> 6) + 4 * p; }
-            else { kk = tid & 15; ii = (tid >> 4) + 16 * p; }
+            a_idx(p, ii, kk);
             As[kk][ii] = ((am >> p) & 1u) ? (TC)ra[p] : (TC)0;
         }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < NP; ++p) {
             int kk, jj;
-            if constexpr (BL == 1) { jj = tid & 63; kk = (tid >> 6) + 4 * p; }
-            else { kk = tid & 15; jj = (tid >> 4) + 16 * p; }
+            b_idx(p, kk, jj);
             Bs[kk][jj] = ((bm >> p) & 1u) ? (TC)rb[p] : (TC)0;
         }
     };
 
+    constexpr int NBK = 2 * WT;  // MFMA blocks per wave along each edge
     const int wm = wave & 1, wn = wave >> 1;
-    V4 acc[2][2];
+    V4 acc[NBK][NBK];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NBK; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+        for (int b = 0; b < NBK; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
     const int li = lane & 15, lk = lane >> 4;
     if (kbeg < kend) fetch(kbeg);
@@ -152,15 +165,15 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
 #pragma unroll
         for (int kq = 0; kq < TK / 4; ++kq) {
             const int kr = kq * 4 + lk;
-            TC av[2], bv[2];
+            TC av[NBK], bv[NBK];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[kr][wm * 32 + a * 16 + li];
+            for (int a = 0; a < NBK; ++a) av[a] = As[kr][wm * 32 * WT + a * 16 + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[kr][wn * 32 + b * 16 + li];
+            for (int b = 0; b < NBK; ++b) bv[b] = Bs[kr][wn * 32 * WT + b * 16 + li];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < NBK; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+                for (int b = 0; b < NBK; ++b) {
                     if constexpr (sizeof(TC) == 8)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
                     else
@@ -171,13 +184,13 @@ __global__ __launch_bounds__(256) void k_gemm(Args g)
 
     TCS *Cp = (TCS *)g.C;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NBK; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NBK; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = tm0 + wm * 32 + a * 16 + d_row<TC>(lk, r);
-                const int64_t j = tn0 + wn * 32 + b * 16 + li;
+                const int64_t i = tm0 + wm * 32 * WT + a * 16 + d_row<TC>(lk, r);
+                const int64_t j = tn0 + wn * 32 * WT + b * 16 + li;
                 if (i >= g.m || j >= g.n) continue;
                 if (g.part) {  // split-K partial: plain sum, alpha/beta applied by the reduction
                     g.part[((int64_t)blockIdx.z * g.n + j) * g.m + i] = (double)acc[a][b][r];
@@ -409,11 +422,20 @@ __global__ void k_splitk_reduce(const double *__restrict__ part, int nz, int64_t
     *cp = (TCS)v;
 }
 
+// Tile choice: 128x128 where both edges are large (>= g_big_min) and the
+// grid still fills the GPU; 0 disables the large tiles.
+int64_t g_big_min = 2048;
+
 template <typename TC, typename TA, typename TB, typename TCS, int AL, int BL>
 int run(const Args &a, int nz, hipStream_t st)
 {
-    dim3 grid((unsigned)cdiv(a.m, TM), (unsigned)cdiv(a.n, TN), (unsigned)nz);
-    hipLaunchKernelGGL((k_gemm<TC, TA, TB, TCS, AL, BL>), grid, dim3(256), 0, st, a);
+    if (g_big_min > 0 && a.m >= g_big_min && a.n >= g_big_min) {
+        dim3 grid((unsigned)cdiv(a.m, 2 * TM), (unsigned)cdiv(a.n, 2 * TN), (unsigned)nz);
+        hipLaunchKernelGGL((k_gemm<TC, TA, TB, TCS, AL, BL, 2>), grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((unsigned)cdiv(a.m, TM), (unsigned)cdiv(a.n, TN), (unsigned)nz);
+        hipLaunchKernelGGL((k_gemm<TC, TA, TB, TCS, AL, BL, 1>), grid, dim3(256), 0, st, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
 }
 
@@ -507,6 +529,9 @@ int launch_gemm(const GemmDesc &d, hipStream_t st)
 }
 
 int launch_gemm_f64(const GemmDesc &d, hipStream_t st) { return launch_gemm(d, st); }
+
+void gemm_set_big_min(int64_t m) { g_big_min = m; }
+int64_t gemm_big_min() { return g_big_min; }
 
 int64_t gemm_splitk_parts(const GemmDesc &d)
 {

@@ -80,6 +80,8 @@ def test_null_context_is_rejected_without_gpu(gs):
     assert gs.gsyeig_refine(None, 10, 2, 4, 1, 10, 1, 10, 1, 10, None, 1, 10, 1, 1, 10)[0] == -1
     assert gs.gsyeig_set_spin_limit(None, 1) == -1
     assert gs.gsyeig_sync(None) == -1
+    assert gs.gsyeig_autotune(None, 100)[0] == -1
+    assert gs.gsyeig_set_trsv_sweep(None, 0) == -1
     assert gs.gsyeig_destroy(None) == -1
     assert gs.lib().gsyeig_opts_default(None) == -1
 
@@ -93,7 +95,7 @@ def test_binding_refuses_cpu_tensors(gs):
 def test_binding_structs_match_the_header(gs, tmp_path):
     """The ctypes mirrors of gsyeig_opts and gsyeig_info have the C layout:
     sizes and every field offset, as a C compiler lays out the header."""
-    fields = {"gsyeig_opts": gs.gsyeig_opts, "gsyeig_info": gs.gsyeig_info}
+    fields = {"gsyeig_opts": gs.gsyeig_opts, "gsyeig_info": gs.gsyeig_info, "gsyeig_tuning": gs.gsyeig_tuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for st, cls in fields.items():
         lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
