@@ -119,6 +119,8 @@ def main():
                     help="comma-separated s values: time the variants (--sweep-variants) against s on the config's "
                          "input (the shape of the paper's Figs. 1-2); one JSON line per point, no headline line")
     ap.add_argument("--sweep-variants", default="ki,ke,td", help="variants of --sweep-s")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="run only GS2 (form C) and GS1 at the config's n (FP64), for MFMA counter passes; no JSON")
     ap.add_argument("--trsv-only", action="store_true",
                     help="run only KI1/KI3 at the config's n on a random factor, plus a device copy of n^2 doubles "
                          "(the fixed-size reference kernel for hardware byte counters); prints timings, no JSON")
@@ -139,6 +141,8 @@ def main():
     cfg = dict(CONFIGS[args.config])
     if args.trsv_only:
         return trsv_only(args, cfg)
+    if args.gemm_only:
+        return gemm_only(args, cfg)
     if args.n or args.s:
         cfg["n"] = args.n or cfg["n"]
         cfg["s"] = args.s or cfg["s"]
@@ -464,10 +468,51 @@ def trsv_only(args, cfg):
                     rc = gs.gsyeig_trsv(sv.ctx, n, U, n, trans, b, x)
                 if rc:
                     raise gs.GsyeigError("gsyeig_trsv_lp" if lp else "gsyeig_trsv", rc)
+        # the whole operator of the Lanczos loop (KI1, KI2's tile pass, KI3
+        # summing KI2's partials) on a symmetric A
+        A = torch.randn(n, n, generator=g, device=dev, dtype=torch.float64)
+        A = A + A.t()
+        A32 = A.float() if lp else None
+        for _ in range(max(1, args.steps)):
+            rc = (gs.gsyeig_apply_op_lp(sv.ctx, n, A32, n, U32, n, b, x) if lp else
+                  gs.gsyeig_apply_op(sv.ctx, n, A, n, U, n, b, x))
+            if rc:
+                raise gs.GsyeigError("gsyeig_apply_op", rc)
+        del A, A32
         C.copy_(U)  # reads and writes 8 n^2 bytes
         torch.cuda.synchronize()
-    log(f"trsv-only n={n} ({'FP32' if lp else 'FP64'} factor): {2 * max(1, args.steps)} solves and one copy of "
-        f"{8 * n * n} bytes done")
+    log(f"trsv-only n={n} ({'FP32' if lp else 'FP64'} factor): {2 * max(1, args.steps)} solves, "
+        f"{max(1, args.steps)} operator applications and one copy of {8 * n * n} bytes done")
+
+
+def gemm_only(args, cfg):
+    """The matrix-core products alone, for hardware counter passes: GS2
+    (C = U^-T A U^-1, two block solves with n right-hand sides) and one GS1
+    (Cholesky) at the config's n, FP64."""
+    import torch
+
+    import paper_1111_6374_amd as gs
+
+    n = args.n or cfg["n"]
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(6374)
+    U = torch.triu(torch.randn(n, n, generator=g, device=dev, dtype=torch.float64) / math.sqrt(n), 1)
+    U.diagonal().copy_(1.0 + torch.rand(n, generator=g, device=dev, dtype=torch.float64))
+    A = torch.randn(n, n, generator=g, device=dev, dtype=torch.float64)
+    A = A + A.t()
+    C = torch.empty_like(A)
+    with gs.Solver() as sv:
+        for _ in range(max(1, args.steps)):
+            rc = gs.gsyeig_form_c(sv.ctx, n, A, n, U, n, C, n)
+            if rc:
+                raise gs.GsyeigError("gsyeig_form_c", rc)
+        B = torch.matmul(U.t().contiguous(), U)
+        rc = gs.gsyeig_potrf(sv.ctx, n, B, n)
+        if rc:
+            raise gs.GsyeigError("gsyeig_potrf", rc)
+        torch.cuda.synchronize()
+    log(f"gemm-only n={n}: {max(1, args.steps)} GS2 and one GS1 done")
 
 
 def bench_block(args, cfg):

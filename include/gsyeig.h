@@ -191,9 +191,9 @@ typedef struct {
                            /*   output edges are >= this (0: 64x64 tiles only)     */
     double op_ms;          /* measured operator application (KI1-KI3) of the choice */
     double gemm_ms;        /* measured n x n x 256 product of the choice            */
-    double op_ms_cand[3];  /* operator with (512, queue), (512, per tile), (64)     */
-                           /*   sweeps (FP32 storage: the 64-row chain is not used, */
-                           /*   entry 2 is 0)                                       */
+    double op_ms_cand[5];  /* operator with 512-row sweeps of kinds 0..3, then the */
+                           /*   64-row chain (FP32 storage: the 64-row chain is not */
+                           /*   used, entry 4 is 0)                                 */
     double gemm_ms_cand[2];/* product with 128x128 tiles allowed, and without       */
 } gsyeig_tuning;
 
@@ -221,13 +221,15 @@ int gsyeig_destroy(gsyeig_ctx *ctx);
 int gsyeig_set_trsv_block(gsyeig_ctx *ctx, int64_t rows);
 
 /* Kernel design of the 512-row super-block sweeps (KI1/KI3) on this
- * context: 0 (default) = work-queue sweeps -- the panel products with
- * already-solved super-blocks are separate queue items taken in the order
- * the chain needs them, so the links wait only on their neighbours' values
- * (k_trsv_q.hip); 1 = one persistent workgroup per 64-row tile that streams
- * its whole panel as the values arrive (k_trsv_w.hip).  Both compute the
- * same solve with the same operation order per output up to the grouping
- * of the panel sums.  Host-only setting; returns 0, -1 (NULL ctx) or -2. */
+ * context.  Work-queue sweep: the panel products with already-solved
+ * super-blocks are separate queue items taken in the order the chain needs
+ * them, so the links wait only on their neighbours' values (k_trsv_q.hip);
+ * per-tile sweep: one persistent workgroup per 64-row tile streams its
+ * whole panel as the values arrive (k_trsv_w.hip).  kind 0 (default) =
+ * both sweeps work-queue, 1 = both per-tile, 2 = KI1 per-tile and KI3
+ * work-queue, 3 = KI1 work-queue and KI3 per-tile.  All compute the same
+ * solve up to the grouping of the panel sums.  Host-only setting; returns
+ * 0, -1 (NULL ctx) or -2 (kind outside 0..3). */
 int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind);
 
 /* Project-written autotuner: picks the kernel variants of this library for

@@ -87,7 +87,7 @@ class gsyeig_info(ctypes.Structure):
 class gsyeig_tuning(ctypes.Structure):
     _fields_ = [("n_bucket", ctypes.c_int64), ("prec", ctypes.c_int), ("trsv_block", ctypes.c_int),
                 ("trsv_sweep", ctypes.c_int), ("from_cache", ctypes.c_int), ("gemm_big_min", ctypes.c_int64),
-                ("op_ms", ctypes.c_double), ("gemm_ms", ctypes.c_double), ("op_ms_cand", ctypes.c_double * 3),
+                ("op_ms", ctypes.c_double), ("gemm_ms", ctypes.c_double), ("op_ms_cand", ctypes.c_double * 5),
                 ("gemm_ms_cand", ctypes.c_double * 2)]
 
     def as_dict(self):

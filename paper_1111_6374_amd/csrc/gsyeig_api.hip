@@ -193,10 +193,13 @@ static int dinv_from_u(gsyeig_ctx *ctx, int64_t n, const double *U, int64_t ldu,
 // The super-block sweeps on U = D (I + W) (W FP64 or FP32): the work-queue
 // kernels (default) or one workgroup per tile (gsyeig_set_trsv_sweep).
 // KI3 takes b, or (b == nullptr) the SYMV tile partials Pr / Pc.
+static bool queue_n(const gsyeig_ctx *ctx) { return ctx->trsv_sweep == 0 || ctx->trsv_sweep == 3; }
+static bool queue_t(const gsyeig_ctx *ctx) { return ctx->trsv_sweep == 0 || ctx->trsv_sweep == 2; }
+
 static int sweep_n(gsyeig_ctx *ctx, int64_t n, const void *W, int w_f32, int64_t ldw, const double *sb,
                    const double *b, double *x)
 {
-    if (ctx->trsv_sweep == 0) {
+    if (queue_n(ctx)) {
         TrsvQ q;
         TRY(trsvq_prepare(ctx, n, &q));
         return w_f32 ? launch_trsvq_n_f32((const float *)W, ldw, n, sb, b, x, ctx->ctl_n, q, ctx->stream)
@@ -209,7 +212,7 @@ static int sweep_n(gsyeig_ctx *ctx, int64_t n, const void *W, int w_f32, int64_t
 static int sweep_t(gsyeig_ctx *ctx, int64_t n, const void *W, int w_f32, int64_t ldw, const double *sb,
                    const double *b, const double *Pr, const double *Pc, int maxch, int ch, double *x)
 {
-    if (ctx->trsv_sweep == 0) {
+    if (queue_t(ctx)) {
         TrsvQ q;
         TRY(trsvq_prepare(ctx, n, &q));
         return w_f32 ? launch_trsvq_t_f32((const float *)W, ldw, n, sb, b, Pr, Pc, maxch, ch, x, ctx->ctl_t, q,
@@ -1131,7 +1134,7 @@ static int autotune_measure(gsyeig_ctx *ctx, int64_t nm, int prec, double *U, do
     double *tmp = (double *)p;
     const int64_t save_block = ctx->trsv_block;
     const int save_sweep = ctx->trsv_sweep;
-    struct Cand { int block, sweep; } cands[3] = {{512, 0}, {512, 1}, {64, 0}};
+    struct Cand { int block, sweep; } cands[5] = {{512, 0}, {512, 1}, {512, 2}, {512, 3}, {64, 0}};
     float *U32 = nullptr;
     if (prec == GSYEIG_MIXED) {
         TRY(ws_get(ctx, WS_U32, sizeof(float) * (size_t)ld * (size_t)nm, &p));
@@ -1139,7 +1142,7 @@ static int autotune_measure(gsyeig_ctx *ctx, int64_t nm, int prec, double *U, do
         TRY(launch_to_f32(U, ld, U32, ld, nm, nm, ctx->stream));
     }
     double best = 1e300;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 5; ++c) {
         t->op_ms_cand[c] = 0.0;
         if (prec == GSYEIG_MIXED && cands[c].block == 64) continue;  // FP32 storage: super-block sweeps only
         ctx->trsv_block = cands[c].block;
@@ -1259,7 +1262,7 @@ int gsyeig_autotune(gsyeig_ctx *ctx, int64_t n, int prec, const char *cache_path
 int gsyeig_set_trsv_sweep(gsyeig_ctx *ctx, int kind)
 {
     if (!ctx) return -1;
-    if (kind != 0 && kind != 1) return -2;
+    if (kind < 0 || kind > 3) return -2;
     ctx->trsv_sweep = kind;
     return 0;
 }

@@ -35,9 +35,9 @@ def test_autotune_measures_applies_and_caches(orc, tmp_path):
             rc, t = gs.gsyeig_autotune(sv.ctx, 3000, prec, str(cache))
             assert rc == 0 and t.from_cache == 0 and t.n_bucket == 4096 and t.prec == prec
             cands = [c for c in t.op_ms_cand if c > 0]
-            assert len(cands) == (3 if prec == gs.GSYEIG_FP64 else 2)
+            assert len(cands) == (5 if prec == gs.GSYEIG_FP64 else 4)
             assert t.op_ms == min(cands) and t.gemm_ms == min(t.gemm_ms_cand)
-            assert t.trsv_block in (64, 512) and t.trsv_sweep in (0, 1) and t.gemm_big_min in (0, 2048)
+            assert t.trsv_block in (64, 512) and t.trsv_sweep in (0, 1, 2, 3) and t.gemm_big_min in (0, 2048)
             rc, t2 = gs.gsyeig_autotune(sv.ctx, 2500, prec, str(cache))
             assert rc == 0 and t2.from_cache == 1
             assert (t2.trsv_block, t2.trsv_sweep, t2.gemm_big_min) == (t.trsv_block, t.trsv_sweep, t.gemm_big_min)

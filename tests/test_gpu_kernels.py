@@ -362,3 +362,40 @@ def test_check_matches_oracle_metrics(gs, ctx, torch, orc):
     assert rc == 0
     assert abs(info2.eta_max - info.eta_max) <= 1e-10 * info.eta_max
     assert abs(info2.normB_f - info.normB_f) <= 1e-12 * info.normB_f
+
+
+@pytest.mark.parametrize("n", [1537, 4097])
+def test_sweep_kinds_agree(gs, ctx, torch, orc, n):
+    """The four combinations of the two super-block sweep designs (work
+    queue, one workgroup per tile) for KI1 and KI3 give the same solves and
+    the same operator as the oracle; each design is bitwise reproducible."""
+    say("sweep kinds", n)
+    assert gs.gsyeig_set_trsv_block(ctx, 512) == 0
+    U = gen.factor_U(n, gen.rng(120, n))
+    A = gen.random_symmetric(n, seed=121)
+    b = gen.rng(122, n).standard_normal(n)
+    Ud, Ad, bd = dev(torch, U), dev(torch, A), dev(torch, b)
+    ref = {0: orc.trsv_upper(U, b), 1: orc.trsv_upper_t(U, b), 2: orc.apply_ki(A, U, b)}
+    out = {}
+    for kind in range(4):
+        assert gs.gsyeig_set_trsv_sweep(ctx, kind) == 0
+        for t in (0, 1, 2):
+            x = torch.empty_like(bd)
+            x2 = torch.empty_like(bd)
+            if t < 2:
+                assert gs.gsyeig_trsv(ctx, n, Ud, n, t, bd, x) == 0
+                assert gs.gsyeig_trsv(ctx, n, Ud, n, t, bd, x2) == 0
+            else:
+                assert gs.gsyeig_apply_op(ctx, n, Ad, n, Ud, n, bd, x) == 0
+                assert gs.gsyeig_apply_op(ctx, n, Ad, n, Ud, n, bd, x2) == 0
+            assert gs.gsyeig_sync(ctx) == 0
+            assert torch.equal(x, x2)
+            xh = host(x)
+            scale = np.max(np.abs(ref[t]))
+            assert np.max(np.abs(xh - ref[t])) <= 64 * n * U64 * max(scale, 1.0) * (10.0 if t == 2 else 1.0)
+            out[(kind, t)] = xh
+    assert gs.gsyeig_set_trsv_sweep(ctx, 0) == 0
+    assert gs.gsyeig_set_trsv_sweep(ctx, 4) == -2
+    for kind in (1, 2, 3):
+        for t in (0, 1, 2):
+            assert np.max(np.abs(out[(kind, t)] - out[(0, t)])) <= 1e-12 * max(np.max(np.abs(out[(0, t)])), 1.0)
