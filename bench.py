@@ -25,8 +25,8 @@ CONFIGS = {
     2: dict(n=32768, s=200, law="clustered", prec="mixed",
             label="known-spectrum pencil n=32768 s=200, clustered spectrum, mixed FP32 sweeps + FP64 refinement"),
     3: dict(n=65536, s=800, law="spaced", prec="mixed", block=32,
-            label="known-spectrum pencil n=65536 s=800 + 1-D FEM pencil (inverse pencil), block Lanczos, "
-                  "mixed FP32 block products + FP64 refinement"),
+            label="known-spectrum pencil n=65536 s=800 with eigenvectors Y = I - 2 Q Q^T (Q orthonormal, rank 256) "
+                  "+ 1-D FEM pencil (inverse pencil), block Lanczos, mixed FP32 block products + FP64 refinement"),
     4: dict(n=0, s=0, law="spaced", label="batched known-spectrum pencils, n ~ U{256..4096}, s = ceil(0.05 n)"),
 }
 HBM_PEAK_GBS = 8000.0
@@ -60,22 +60,31 @@ def measured_traffic(kernel, n, prec):
     return None
 
 
-def cpu_baseline(n_target, law="spaced"):
-    """The oracle (plain C, FP64) on a bounded sample: a full solve at n = 2048
-    of the same generator, scaled by (n_target / 2048)^3 (every stage is O(n^3))."""
+def cpu_baseline(n_target, law="spaced", sizes=(768, 1024, 1536, 2048)):
+    """The oracle (plain C, FP64) on a bounded sample: full solves of the same
+    generator at a few sizes (s = ceil(0.006 n), the config's ratio), a
+    least-squares fit of log t = log c + e log n over them, extrapolated to
+    n_target.  Every stage is O(n^3), so e should come out close to 3; the
+    fitted exponent is reported with the sample."""
     import gen
+    import numpy as np
     import oracle
 
-    n, s = 2048, 13
-    d = gen.known_spectrum(n, law, seed=gen.BASE_SEED, stream=(1, 0, 99))
     oracle.lib()
-    t0 = time.perf_counter()
-    oracle.gsyeig(d["A"], d["B"], s)
-    t = time.perf_counter() - t0
+    ts = []
+    for n in sizes:
+        s = max(1, math.ceil(0.006 * n))
+        d = gen.known_spectrum(n, law, seed=gen.BASE_SEED, stream=(1, 0, 99, n))
+        t0 = time.perf_counter()
+        oracle.gsyeig(d["A"], d["B"], s)
+        ts.append(time.perf_counter() - t0)
+    e, logc = np.polyfit(np.log(np.array(sizes, dtype=float)), np.log(np.array(ts)), 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": t * (n_target / n) ** 3, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"full oracle solve n={n} s={s} (same generator) took {t:.2f} s, "
-                      f"scaled by (n/{n})^3 to n={n_target}"}
+    pts = ", ".join(f"n={n}: {t:.2f} s" for n, t in zip(sizes, ts))
+    return {"value": float(math.exp(logc) * n_target ** e), "unit": "s", "cores": threads, "kind": "oracle",
+            "extrapolated": True,
+            "sample": f"full oracle solves of the same generator ({pts}); fit t = c n^e gives e = {e:.2f}, "
+                      f"extrapolated to n={n_target}"}
 
 
 def main():

@@ -5,8 +5,8 @@
  *        A X = B X Lambda,   A = A^T,  B = B^T positive definite,      (Eq. 1)
  *
  * for the s algebraically smallest (or largest) eigenpairs, s << n, by the
- * paper's variant KI (Section 2.3, "Krylov-subspace with implicit operation
- * on C"; Table 1 keys GS1, KI1-KI5, BT1):
+ * paper's variant KI (Section 2.3: a Krylov method that applies C only
+ * implicitly, through the factor; Table 1 keys GS1, KI1-KI5, BT1):
  *
  *   GS1  B = U^T U, U upper triangular                          (Eq. 2)
  *   KI1  wbar = U^-1 w          (triangular solve)
@@ -415,8 +415,8 @@ int gsyeig_trsm_lp(gsyeig_ctx *ctx, int64_t n, const float *U, int64_t ldu, int 
                    const double *V, int64_t ldv, double *X, int64_t ldx);
 
 /* Dense symmetric eigensolver for the small projected matrices of the
- * refinement (Rayleigh-Ritz, Section 2.3 step "eigenpairs of the projected
- * matrix"): the nwant smallest (which = 0) or largest (which = 1)
+ * refinement (the Rayleigh-Ritz step of Section 2.3, which solves the small
+ * projected problem): the nwant smallest (which = 0) or largest (which = 1)
  * eigenpairs of the symmetric N x N matrix H (device, column-major, ldh;
  * only read), N <= 8192, by Householder tridiagonalisation, Sturm bisection,
  * inverse iteration (made orthonormal by Cholesky QR twice; Gram-Schmidt in

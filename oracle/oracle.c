@@ -23,7 +23,7 @@
  *   - a plain Lanczos run on the implicit operator C w = U^-T(A(U^-1 w))
  *     (variant KI, Sec. 2.3; Table 1 keys KI1-KI4) with classical
  *     Gram-Schmidt re-orthogonalisation applied twice, in the paper's order:
- *     three-term recurrence first, then "orthogonalise twice".
+ *     three-term recurrence first, then Gram-Schmidt applied twice.
  *
  * All matrices are dense, row-major, leading dimension n.  OpenMP is used
  * only over independent output rows/columns, so results do not depend on the

@@ -2,8 +2,8 @@
 // variant KI, Section 2.3 and Table 1), in FP64:
 //
 //   z := z - beta_{k-1} w_{k-1};  alpha_k := w_k^T z;  z := z - alpha_k w_k
-//   twice:  h := V_k^T z;  z := z - V_k h      (classical Gram-Schmidt, the
-//                                               "orthogonalise twice" rule)
+//   twice:  h := V_k^T z;  z := z - V_k h      (classical Gram-Schmidt applied
+//                                               twice, Kahan's rule)
 //   beta_k := ||z||;  w_{k+1} := z / beta_k
 //
 // The basis V (n x (m+1), column-major, each Lanczos vector contiguous) is
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *w
     if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
 }
 
-// Partial re-orthogonalisation (Simon 1984; Sec. 2.3's "monitor the
-// orthogonality and amend it when lost"): omega_j,k estimates w_j^T w_k.  From
+// Partial re-orthogonalisation (Simon 1984; Section 2.3 asks that the loss
+// of orthogonality be watched and repaired): omega_j,k estimates w_j^T w_k.  From
 // the Lanczos relation beta_k w_{k+1} = C w_k - alpha_k w_k - beta_{k-1} w_{k-1}
 // and the same relation for w_j,
 //   beta_k om_{j,k+1} = beta_j om_{j+1,k} + (alpha_j - alpha_k) om_{j,k}
