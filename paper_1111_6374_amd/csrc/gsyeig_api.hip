@@ -62,6 +62,15 @@ static int ctl_clear_err(gsyeig_ctx *ctx)
 {
     HIP_TRY(hipMemsetAsync(&ctx->ctl_n->err, 0, sizeof(unsigned), ctx->stream));
     HIP_TRY(hipMemsetAsync(&ctx->ctl_t->err, 0, sizeof(unsigned), ctx->stream));
+    HIP_TRY(hipMemsetAsync(&ctx->ctl_lz->err, 0, sizeof(unsigned), ctx->stream));
+    return 0;
+}
+
+// the fused Lanczos step's queue: counters zero, the context's spin bound
+static int lzctl_init(gsyeig_ctx *ctx)
+{
+    HIP_TRY(hipMemsetAsync(ctx->ctl_lz, 0, sizeof(LzCtl), ctx->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_lz->spin, (int)ctx->spin_limit, 1, ctx->stream));
     return 0;
 }
 
@@ -90,13 +99,15 @@ static int ctl_check(gsyeig_ctx *ctx)
     HIP_TRY(hipMemcpyAsync(h, &ctx->ctl_n->err, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipMemcpyAsync(h + 1, &ctx->ctl_t->err, sizeof(unsigned), hipMemcpyDeviceToHost,
                            ctx->stream));
+    HIP_TRY(hipMemcpyAsync(h + 2, &ctx->ctl_lz->err, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (h[0] || h[1]) {
-        // a wait expired: restart both control blocks and the queue sweeps'
+    if (h[0] || h[1] || h[2]) {
+        // a wait expired: restart the control blocks and the queue sweeps'
         // partial buffers from a clean state
         ctx->trsvq_n = -1;
         int rc;
-        if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)))
+        if ((rc = ctl_init(ctx, ctx->ctl_n, ctx->ctl_rows)) || (rc = ctl_init(ctx, ctx->ctl_t, ctx->ctl_rows)) ||
+            (rc = lzctl_init(ctx)))
             return rc;
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         return GSYEIG_ESPIN;
@@ -442,6 +453,7 @@ struct LzBufs {
     int reorth;      // 0: always two passes; 1: second pass when needed; 2: partial (omega estimates)
     double *om;      // reorth 2: three omega vectors of length ldom, and the ||T|| estimate after them
     int64_t ldom;
+    double *slots;   // reorth 2: the published partial sums of the fused step (sentinel-initialised)
 };
 
 static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
@@ -461,6 +473,7 @@ static int lz_bufs(gsyeig_ctx *ctx, int64_t n, int64_t kmax, LzBufs *b)
     b->red2 = b->z0part + lz_z0_parts(n) + 64;
     b->reorth = 1;
     b->om = nullptr;
+    b->slots = nullptr;
     b->ldom = 0;
     TRY(ws_get(ctx, WS_RED2, sizeof(double) * (size_t)(kmax + 8), &p));
     b->h = (double *)p;
@@ -477,16 +490,13 @@ static int lz_step(gsyeig_ctx *ctx, int64_t n, const LzOp &op, double *V, int64_
     if (b.reorth == 2) {
         // both passes only on the steps where the omega estimates of w_j^T w_{k+1}
         // exceed sqrt(u), and on the step after each of them
-        TRY(launch_lz_alpha(b.z, wp, wk, alpha, beta, k, n, b.red, ctx->stream, b.z0part));
+        // (two launches: alpha_k, the omega recurrence, beta_k and w_{k+1};
+        // the two passes, only on the steps that ask for them)
         double *om_c = b.om + (k % 3) * b.ldom, *om_n = b.om + ((k + 1) % 3) * b.ldom;
         const double *om_p = b.om + ((k + 2) % 3) * b.ldom;
-        TRY(launch_pro_omega(alpha, beta, k, b.z0part, n, om_p, om_c, om_n, b.om + 3 * b.ldom, b.flag,
-                             ctx->stream));
-        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, nullptr, ctx->stream, b.flag));
-        TRY(launch_cgs_pass(V, ldv, n, k + 1, b.z, b.red2, b.h, b.normpart, ctx->stream, b.flag));
-        TRY(launch_lz_normalize_sel(b.z, V + (k + 1) * ldv, beta, k, n, b.normpart, b.z0part, b.flag,
-                                    ctx->stream));
-        return 0;
+        return launch_lz_post(b.z, wp, wk, V + (k + 1) * ldv, alpha, beta, k, n, V, ldv, om_p, om_c, om_n,
+                              b.om + 3 * b.ldom, b.flag, b.slots, b.slots + lz_post_slots(), b.ldom, ctx->ctl_lz,
+                              ctx->stream);
     }
     if (b.reorth) {
         // second pass only where the first lost more than 1/sqrt(2) of the norm
@@ -537,9 +547,12 @@ static int lz_solve_body(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, co
     b.reorth = (int)o->reorth;
     if (b.reorth == 2) {
         b.ldom = mmax + 8;
-        TRY(ws_get(ctx, WS_PRO, sizeof(double) * (size_t)(3 * b.ldom + 8), &p));
+        const size_t sent = (size_t)lz_post_slots() + (size_t)lz_cgs_doubles(n, b.ldom);
+        TRY(ws_get(ctx, WS_PRO, sizeof(double) * ((size_t)(3 * b.ldom + 8) + sent), &p));
         b.om = (double *)p;
+        b.slots = b.om + 3 * b.ldom + 8;
         TRY(launch_pro_init(b.om, b.om + 3 * b.ldom, b.flag, ctx->stream));
+        HIP_TRY(hipMemsetAsync(b.slots, 0xFF, sizeof(double) * sent, ctx->stream));
     } else {
         HIP_TRY(hipMemsetAsync(b.flag, 0, 4 * sizeof(int), ctx->stream));
     }
@@ -1068,7 +1081,9 @@ int gsyeig_create(gsyeig_ctx **ctx_out, void *hip_stream)
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     for (int i = 0; i < 64; ++i)
         if (hipEventCreate(&ctx->pev[i]) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
+    if (hipMalloc((void **)&ctx->ctl_lz, sizeof(LzCtl)) != hipSuccess) { delete ctx; return GSYEIG_EHIP; }
     int rc = ctl_reserve(ctx, 65536);
+    if (!rc) rc = lzctl_init(ctx);
     if (rc) { delete ctx; return rc; }
     void *scr;  // set-up of gsyeig_symv_noalloc on this device (its scratch array's address)
     if ((rc = noalloc_scratch(&scr))) { delete ctx; return rc; }
@@ -1088,6 +1103,7 @@ int gsyeig_destroy(gsyeig_ctx *ctx)
         if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
     if (ctx->ctl_n) (void)hipFree(ctx->ctl_n);
     if (ctx->ctl_t) (void)hipFree(ctx->ctl_t);
+    if (ctx->ctl_lz) (void)hipFree(ctx->ctl_lz);
     if (ctx->dscal) (void)hipFree(ctx->dscal);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
     for (int i = 0; i < 10; ++i)
@@ -1273,6 +1289,7 @@ int gsyeig_set_spin_limit(gsyeig_ctx *ctx, unsigned limit)
     ctx->spin_limit = limit;
     HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_n->spin, (int)limit, 1, ctx->stream));
     HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_t->spin, (int)limit, 1, ctx->stream));
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)&ctx->ctl_lz->spin, (int)limit, 1, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return 0;
 }

@@ -81,6 +81,7 @@ struct gsyeig_ctx {
     size_t ws_bytes[WS_COUNT];
     PCtl *ctl_n;        // persistent-kernel control blocks (+flags)
     PCtl *ctl_t;
+    struct LzCtl *ctl_lz;  // the fused Lanczos step's queue (k_lanczos.hip)
     int64_t ctl_rows;   // staging capacity (rows) of each staging vector
     int64_t trsv_block; // 64: chained 64-row solves; 512: super-block solves
     int trsv_sweep;     // super-block solves: 0 = work-queue sweeps, 1 = one workgroup per tile
@@ -248,17 +249,33 @@ int launch_lz_alpha(double *z, const double *wprev, const double *wk, double *al
 int launch_cgs_pass(const double *V, int64_t ldv, int64_t n, int64_t kcols, double *z, double *part,
                     double *h, double *normpart, hipStream_t st, const int *run = nullptr);
 int lz_z0_parts(int64_t n);
+// Control block of the fused post-operator Lanczos step (k_lanczos.hip):
+// queue ticket, workgroups done, sticky wait-expiry flag, spin bound (0 =
+// SPIN_LIMIT), phase counters; zero between launches (the last workgroup
+// resets it).
+struct LzCtl {
+    unsigned ticket, done, err, spin;
+    unsigned ph[12];
+};
+// Two launches after the operator on each step with partial
+// re-orthogonalisation: alpha_k, the omega recurrence and (when it asks for
+// none) beta_k and w_{k+1}; then, only when it asks for them, two
+// Gram-Schmidt passes and w_{k+1}.  slots (lz_post_slots doubles) and cgs
+// (lz_cgs_doubles(n, kcap), k + 1 <= kcap) all STAGE_SENTINEL before the
+// first step of a run; GSYEIG_ETOOBIG for n > 2^21.
+int launch_lz_post(double *z, const double *wprev, const double *wk, double *wnext, double *alpha, double *beta,
+                   int64_t k, int64_t n, const double *V, int64_t ldv, const double *omP, const double *omC,
+                   double *omN, double *anorm, int *flag, double *slots, double *cgs, int64_t kcap, LzCtl *ctl,
+                   hipStream_t st);
+int lz_post_slots();
+int64_t lz_cgs_doubles(int64_t n, int64_t kcap);
 // *flag = 1 if the first pass shrank z below 1/sqrt(2) of its norm
 int launch_reorth_flag(const double *z0part, int64_t n, const double *z1part, int *flag, hipStream_t st);
 int launch_lz_normalize(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
                         const double *normpart, hipStream_t st);
-// partial re-orthogonalisation: omega recurrence and the decision flag
-// flag: [0] orthogonalise this step, [1] count of such steps, [2] force next
+// partial re-orthogonalisation: start of the omega estimates; flag: [0]
+// orthogonalise this step, [1] count of such steps, [2] force the next
 int launch_pro_init(double *om0, double *anorm, int *flag, hipStream_t st);
-int launch_pro_omega(const double *alpha, const double *beta, int64_t k, const double *z0part, int64_t n,
-                     const double *omP, const double *omC, double *omN, double *anorm, int *flag, hipStream_t st);
-int launch_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
-                            const double *normpart, const double *z0part, const int *flag, hipStream_t st);
 
 // tridiagonal eigensolver (KI5)
 int launch_tri_bisect(const double *alpha, const double *beta, int64_t m, int64_t nwant, int which,

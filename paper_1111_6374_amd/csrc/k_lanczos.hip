@@ -272,6 +272,43 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *w
     if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
 }
 
+__global__ void k_pro_init(double *om0, double *anorm, int *flag)
+{
+    if (threadIdx.x == 0) {
+        om0[0] = 1.0;
+        *anorm = 0.0;
+        flag[0] = flag[1] = flag[2] = 0;
+    }
+}
+
+inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The post-operator part of a Lanczos step with partial re-orthogonalisation
+// in two launches.
+//
+// k_lz_step (one 1024-thread workgroup per 2048 rows): the three-term
+// update and alpha_k, |z|^2, the omega recurrence and the decision whether
+// this step orthogonalises, and -- when it does not -- beta_k and
+// w_{k+1} = z / beta_k.  A row chunk stays in registers throughout; the
+// two global sums are exchanged through sentinel-initialised slots (each
+// workgroup publishes its partial and polls the others', the omega
+// recurrence is evaluated identically by every workgroup).  The slots come
+// in two sets used by alternate steps, and a workgroup restores its slots
+// of the other set, so no launch needs a host memset.  The grid is small
+// (n / 2048 workgroups) and every workgroup can be resident at once.
+//
+// k_lz_cgs (every workgroup that can run): on the steps that orthogonalise,
+// two classical Gram-Schmidt passes against w_0..w_k and the normalisation;
+// on the others it returns at once.  Its phases are items of one work
+// queue taken in order by whichever workgroups are running, and an item
+// waits only on counters of earlier phases, so it drains whatever the
+// residency: [two passes of (T: V^T z tiles of 8192 rows x 8 columns,
+// R: h = sum of the tiles, N: z -= V h over 64 rows)] [E: w_{k+1}].
+//
+// Summation orders are fixed in both: bitwise reproducible.
 // Partial re-orthogonalisation (Simon 1984; Section 2.3 asks that the loss
 // of orthogonality be watched and repaired): omega_j,k estimates w_j^T w_k.  From
 // the Lanczos relation beta_k w_{k+1} = C w_k - alpha_k w_k - beta_{k-1} w_{k-1}
@@ -287,108 +324,466 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double *z, double *w
 // omP = om_{.,k-1}; beta_k is taken from the unorthogonalised z (z0part).
 // flag[0] = this step orthogonalises, flag[1] counts such steps, flag[2] =
 // the next step must orthogonalise; *anorm = running estimate of ||T||.
-__global__ __launch_bounds__(1024) void k_pro_omega(const double *alpha, const double *beta, int64_t k,
-                                                    const double *z0part, int P0, const double *omP,
-                                                    const double *omC, double *omN, double *anorm, int *flag,
-                                                    double eps1)
+namespace {
+
+constexpr int PR = 2048;   // rows of a k_lz_step workgroup / an E item (1024 threads x 2)
+constexpr int TR = 8192;   // rows of a projection tile (1024 threads x 8)
+constexpr int TC = 8;      // columns of a projection tile
+constexpr int MAXP = 1024; // k_lz_step workgroups at most (n <= 2^21)
+
+// sum over the 1024 threads, returned to all (fixed order)
+__device__ double bsum1024(double v, double *s16)
 {
-    __shared__ double s_red[16];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // beta_k before any orthogonalisation: sum of the partials, fixed order
-    double v = 0.0;
-    for (int p = tid; p < P0; p += 1024) v += z0part[p];
     v = wave_sum(v);
-    if (lane == 0) s_red[wv] = v;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s16[w] = v;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) t += s_red[w];
-    const double bk = sqrt(t);
-    const double ak = alpha[k];
-    const double bkm1 = (k > 0) ? beta[k - 1] : 0.0;
-    const double an = fmax(*anorm, fabs(ak) + bk + bkm1);
-    const double tau = eps1 * an;
+    for (int q = 0; q < 16; ++q) t += s16[q];
+    return t;
+}
+
+// sum of part[0..P-1] (fixed order), returned to all
+__device__ double sum1024(const double *part, int64_t P, double *s16)
+{
+    double v = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += 1024) v += part[p];
+    return bsum1024(v, s16);
+}
+
+// Sum of the P (<= MAXP) published slots (sentinel until written), polled
+// by wave 0 (bounded; an expired wait records the error and reads 0) and
+// summed in a fixed order; returned to every thread.
+__device__ double sum_published(const double *slot, int P, LzCtl *ctl, unsigned lim, double *s1)
+{
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        double acc = 0.0;
+        for (int p0 = 0; p0 < P; p0 += 64 * 16) {
+            unsigned long long v[16];
+            unsigned live = 0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int p = p0 + l + 64 * c;
+                live |= (p < P ? 1u : 0u) << c;
+                v[c] = (p < P) ? __hip_atomic_load(reinterpret_cast<const unsigned long long *>(slot + p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : 0ull;
+            }
+            unsigned it = 0;
+            for (;;) {
+                bool pend = false;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) pend |= ((live >> c) & 1u) && v[c] == STAGE_SENTINEL;
+                if (!__any(pend)) break;
+                if (++it > lim) {
+                    __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        if (v[c] == STAGE_SENTINEL) v[c] = 0ull;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (((live >> c) & 1u) && v[c] == STAGE_SENTINEL)
+                        v[c] = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(slot + p0 + l + 64 * c),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if ((live >> c) & 1u) acc += __longlong_as_double((long long)v[c]);
+        }
+        acc = wave_sum(acc);
+        if (l == 0) *s1 = acc;
+    }
+    __syncthreads();
+    const double r = *s1;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void publish(double *slot, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct LzStep {
+    double *z;
+    const double *wprev, *wk;
+    double *wnext;
+    double *alpha, *beta;
+    int64_t k, n;
+    const double *omP, *omC;
+    double *omN, *anorm;
+    int *flag;
+    double eps1;
+    double *slots;  // 2 sets x (apart[MAXP], z0part[MAXP]), sentinel-initialised
+    LzCtl *ctl;
+};
+
+__global__ __launch_bounds__(1024) void k_lz_step(LzStep a)
+{
+    __shared__ double s16[16], s1;
+    __shared__ double s_in[2];
+    __shared__ int s_forced;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t n = a.n, k = a.k;
+    const int P = (int)gridDim.x, g = (int)blockIdx.x;
+    const unsigned spin = __hip_atomic_load(&a.ctl->spin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned lim = spin ? spin : SPIN_LIMIT;
+    double *cur = a.slots + (k & 1) * 2 * MAXP, *oth = a.slots + ((k + 1) & 1) * 2 * MAXP;
+    // state this step reads and workgroup 0 rewrites at its end: read first
+    if (tid == 0) {
+        s_forced = a.flag[2];
+        s_in[0] = *a.anorm;
+        s_in[1] = (k > 0) ? a.beta[k - 1] : 0.0;
+        // the other set's slots of this workgroup, for the next step
+        publish(oth + g, __longlong_as_double((long long)STAGE_SENTINEL));
+        publish(oth + MAXP + g, __longlong_as_double((long long)STAGE_SENTINEL));
+    }
+    __syncthreads();
+    const double bkm1 = s_in[1];
+    // z := z - beta_{k-1} w_{k-1}; alpha_k = w_k . z
+    double zr[PR / 1024], wr[PR / 1024];
+    double d = 0.0;
+#pragma unroll
+    for (int p = 0; p < PR / 1024; ++p) {
+        const int64_t i = (int64_t)g * PR + tid + 1024 * p;
+        zr[p] = wr[p] = 0.0;
+        if (i < n) {
+            double zi = a.z[i];
+            if (k > 0) zi = fma(-bkm1, a.wprev[i], zi);
+            zr[p] = zi;
+            wr[p] = a.wk[i];
+            d = fma(wr[p], zi, d);
+        }
+    }
+    d = bsum1024(d, s16);
+    if (tid == 0) publish(cur + g, d);
+    const double ak = sum_published(cur, P, a.ctl, lim, &s1);
+    // z := z - alpha_k w_k; beta_k before any orthogonalisation
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < PR / 1024; ++p) {
+        zr[p] = fma(-ak, wr[p], zr[p]);
+        s = fma(zr[p], zr[p], s);
+    }
+    s = bsum1024(s, s16);
+    if (tid == 0) publish(cur + MAXP + g, s);
+    const double bk = sqrt(sum_published(cur + MAXP, P, a.ctl, lim, &s1));
+    // the omega recurrence (every workgroup: the same inputs, the same f)
+    const double an = fmax(s_in[0], fabs(ak) + bk + bkm1);
+    const double tau = a.eps1 * an;
     const double inv = (bk > 0.0) ? 1.0 / bk : 0.0;
     double mx = 0.0;
     for (int64_t j = tid; j < k; j += 1024) {
-        double num = beta[j] * omC[j + 1] + (alpha[j] - ak) * omC[j] - bkm1 * omP[j];
-        if (j > 0) num += beta[j - 1] * omC[j - 1];
+        double num = a.beta[j] * a.omC[j + 1] + (a.alpha[j] - ak) * a.omC[j] - bkm1 * a.omP[j];
+        if (j > 0) num += a.beta[j - 1] * a.omC[j - 1];
         const double o = (num + copysign(tau, num)) * inv;
-        omN[j] = o;
+        if (g == 0) a.omN[j] = o;
         mx = fmax(mx, fabs(o));
     }
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     __syncthreads();
-    if (lane == 0) s_red[wv] = mx;
+    if (lane == 0) s16[wv] = mx;
     __syncthreads();
     mx = 0.0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) mx = fmax(mx, s_red[w]);
-    const int forced = flag[2];
-    // sqrt(u) = 2^-26.5, with u = 2^-53.  A small beta_k (near breakdown) also
-    // loses local orthogonality, om_{k,k+1} = tau / beta_k: orthogonalise then.
+    for (int w = 0; w < 16; ++w) mx = fmax(mx, s16[w]);
+    // sqrt(u) = 2^-26.5, with u = 2^-53.  A small beta_k (near breakdown)
+    // also loses local orthogonality, om_{k,k+1} = tau / beta_k:
+    // orthogonalise then.
+    const int forced = s_forced;
     constexpr double thr = 1.0536712127723509e-08;
     const int f = forced || !(mx <= thr) || (bk * thr < tau);
-    if (f)  // the two passes restore orthogonality to working accuracy
-        for (int64_t j = tid; j < k; j += 1024) omN[j] = eps1;
+#pragma unroll
+    for (int p = 0; p < PR / 1024; ++p) {
+        const int64_t i = (int64_t)g * PR + tid + 1024 * p;
+        if (i < n) {
+            if (f) a.z[i] = zr[p];  // for the Gram-Schmidt passes
+            else a.wnext[i] = zr[p] / bk;
+        }
+    }
+    if (g == 0) {
+        if (f)  // the two passes restore orthogonality to working accuracy
+            for (int64_t j = tid; j < k; j += 1024) a.omN[j] = a.eps1;
+        __syncthreads();
+        if (tid == 0) {
+            a.alpha[k] = ak;
+            if (!f) a.beta[k] = bk;
+            a.omN[k] = f ? a.eps1 : tau * inv;
+            a.omN[k + 1] = 1.0;
+            *a.anorm = an;
+            a.flag[0] = f;
+            a.flag[1] += f;
+            a.flag[2] = f && !forced;
+        }
+    }
+}
+
+struct LzCgs {
+    const double *z;  // z after the three-term update (k_lz_step)
+    double *wnext, *beta;
+    int64_t k, n;
+    const double *V;
+    int64_t ldv;
+    const int *flag;
+    double *sb;       // sentinel buffers: tp[2][rt x kc], hh[2][kc], z1[n], z2[n], np[nn]
+    int64_t kcap;     // kc capacity of tp / hh
+    LzCtl *ctl;
+};
+
+struct CgsPlan {  // item ranges and buffer offsets (derived the same way on every workgroup)
+    int64_t rt, nt, nr, nn, ne, pass, e0, end;
+    int64_t tp, hh, z1, z2, np, total;
+};
+
+__device__ __forceinline__ CgsPlan cgs_plan(int64_t n, int64_t kc, int64_t kcap)
+{
+    CgsPlan p;
+    p.rt = (n + TR - 1) / TR;
+    p.nt = p.rt * ((kc + TC - 1) / TC);
+    p.nr = (kc + 1023) / 1024;
+    p.nn = (n + 63) / 64;
+    p.ne = (n + PR - 1) / PR;
+    p.pass = p.nt + p.nr + p.nn;
+    p.e0 = 2 * p.pass;
+    p.end = p.e0 + p.ne;
+    p.tp = 0;
+    p.hh = 2 * p.rt * kcap;
+    p.z1 = p.hh + 2 * kcap;
+    p.z2 = p.z1 + n;
+    p.np = p.z2 + n;
+    p.total = p.np + p.nn;
+    return p;
+}
+
+// lane `lane`'s v, to every lane (lane wave-uniform)
+__device__ __forceinline__ double rdlane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ unsigned long long ldb(const double *p)
+{
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One published value per lane (ok lanes), polled until it is not the
+// sentinel (bounded: an expired wait records the error and reads 0).
+__device__ __forceinline__ double poll1(const double *p, bool ok, LzCtl *ctl, unsigned lim)
+{
+    unsigned long long v = ok ? ldb(p) : 0ull;
+    unsigned it = 0;
+    while (__any(ok && v == STAGE_SENTINEL)) {
+        if (++it > lim) {
+            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v == STAGE_SENTINEL) v = 0ull;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        if (ok && v == STAGE_SENTINEL) v = ldb(p);
+    }
+    return __longlong_as_double((long long)v);
+}
+
+__global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
+{
+    if (*(volatile const int *)a.flag == 0) return;  // this step does not orthogonalise
+    __shared__ int64_t s_q;
+    __shared__ int s_last;
+    __shared__ double s16[16];
+    __shared__ double s_red[16][64];
+    LzCtl *ctl = a.ctl;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t n = a.n, k = a.k, kc = k + 1;
+    const CgsPlan P = cgs_plan(n, kc, a.kcap);
+    const unsigned spin = __hip_atomic_load(&ctl->spin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned lim = spin ? spin : SPIN_LIMIT;
+    double *sb = a.sb;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_q = (int64_t)__hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int64_t q = s_q;
+        if (q >= P.end) break;
+        if (q < P.e0) {
+            const int pass = q >= P.pass;
+            const int64_t d = q - pass * P.pass;
+            double *tp = sb + P.tp + pass * P.rt * a.kcap, *hh = sb + P.hh + pass * a.kcap;
+            const double *zin = pass ? sb + P.z1 : a.z;
+            double *zout = pass ? sb + P.z2 : sb + P.z1;
+            if (d < P.nt) {
+                // T: tp[rt][c] = V(rows of rt, c)^T z(rows of rt), TC columns
+                const int64_t rt = d % P.rt, c0 = (d / P.rt) * TC;
+                double zr[TR / 1024];
+#pragma unroll
+                for (int p = 0; p < TR / 1024; ++p) {
+                    const int64_t i = rt * TR + tid + 1024 * p;
+                    zr[p] = (i < n) ? (pass ? poll1(zin + i, true, ctl, lim) : zin[i]) : 0.0;
+                }
+                // every load from a clamped in-bounds address (rows beyond n
+                // meet zr = 0; columns beyond kc are never written out)
+#pragma unroll 2
+                for (int c = 0; c < TC; ++c) {
+                    const int64_t cc = (c0 + c < kc) ? c0 + c : kc - 1;
+                    const double *v = a.V + cc * a.ldv;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int p = 0; p < TR / 1024; ++p) {
+                        const int64_t i = rt * TR + tid + 1024 * p;
+                        acc = fma(v[i < n ? i : n - 1], zr[p], acc);
+                    }
+                    acc = wave_sum(acc);
+                    if (lane == 0) s_red[wv][c] = acc;
+                }
+                __syncthreads();
+                if (tid < TC && c0 + tid < kc) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int w = 0; w < 16; ++w) s += s_red[w][tid];
+                    publish(tp + rt * a.kcap + c0 + tid, s);
+                }
+            } else if (d < P.nt + P.nr) {
+                // R: hh[c] = sum of the tiles' projections, in tile order
+                const int64_t c = (d - P.nt) * 1024 + tid;
+                if (c < kc) {
+                    double s = 0.0;
+                    for (int64_t r = 0; r < P.rt; ++r) s += poll1(tp + r * a.kcap + c, true, ctl, lim);
+                    publish(hh + c, s);
+                }
+            } else {
+                // N: z := z - V hh over 64 rows (16 waves split the columns;
+                // a wave polls hh 64 columns at a time and broadcasts lane u's
+                // value for column c0 + u); pass 1 also publishes |z|^2 over the rows
+                const int64_t r = (d - P.nt - P.nr) * 64 + lane;
+                const bool ok = r < n;
+                const int64_t rr = ok ? r : n - 1;
+                const int64_t per = (((kc + 15) / 16 + 63) / 64) * 64;
+                const int64_t cs = wv * per, ce = (cs + per < kc) ? cs + per : kc;
+                const double *Vr = a.V + rr;
+                double acc = 0.0;
+                for (int64_t c0 = cs; c0 < ce; c0 += 64) {
+                    const int64_t cn = (ce - c0 < 64) ? ce - c0 : 64;
+                    const double hv = poll1(hh + c0 + lane, lane < cn, ctl, lim);
+                    int u = 0;
+                    for (; u + 8 <= cn; u += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int x = 0; x < 8; ++x) v[x] = Vr[(c0 + u + x) * a.ldv];
+#pragma unroll
+                        for (int x = 0; x < 8; ++x) acc = fma(v[x], rdlane(hv, u + x), acc);
+                    }
+                    for (; u < cn; ++u) acc = fma(Vr[(c0 + u) * a.ldv], rdlane(hv, u), acc);
+                }
+                s_red[wv][lane] = acc;
+                __syncthreads();
+                if (wv == 0) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int w = 0; w < 16; ++w) sum += s_red[w][lane];
+                    double zn = 0.0;
+                    if (ok) {
+                        zn = (pass ? poll1(zin + r, true, ctl, lim) : zin[r]) - sum;
+                        publish(zout + r, zn);
+                    }
+                    if (pass) {
+                        const double t2 = wave_sum(zn * zn);
+                        if (lane == 0) publish(sb + P.np + r / 64, t2);
+                    }
+                }
+            }
+        } else {
+            // E: beta_k of the orthogonalised z and w_{k+1} = z / beta_k
+            double v = 0.0;
+            for (int64_t p = tid; p < P.nn; p += 1024) v += poll1(sb + P.np + p, true, ctl, lim);
+            const double bk = sqrt(bsum1024(v, s16));
+            const int64_t e = q - P.e0;
+#pragma unroll
+            for (int p = 0; p < PR / 1024; ++p) {
+                const int64_t i = e * PR + tid + 1024 * p;
+                if (i < n) a.wnext[i] = poll1(sb + P.z2 + i, true, ctl, lim) / bk;
+            }
+            if (e == 0 && tid == 0) a.beta[k] = bk;
+        }
+    }
+    // count this workgroup out; the last one restores the sentinels and
+    // resets the queue for the next step
     __syncthreads();
     if (tid == 0) {
-        omN[k] = f ? eps1 : tau * inv;
-        omN[k + 1] = 1.0;
-        *anorm = an;
-        flag[0] = f;
-        flag[1] += f;
-        flag[2] = f && !forced;
+        const unsigned d = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (d == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (s_last) {
+        const unsigned long long S = STAGE_SENTINEL;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int64_t r = 0; r < P.rt; ++r)
+                for (int64_t c = tid; c < kc; c += 1024)
+                    __hip_atomic_store(reinterpret_cast<unsigned long long *>(sb + P.tp + (pass * P.rt + r) * a.kcap + c),
+                                       S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int64_t c = tid; c < kc; c += 1024)
+                __hip_atomic_store(reinterpret_cast<unsigned long long *>(sb + P.hh + pass * a.kcap + c), S,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        for (int64_t i = tid; i < 2 * n + P.nn; i += 1024)
+            __hip_atomic_store(reinterpret_cast<unsigned long long *>(sb + P.z1 + i), S, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
-
-__global__ void k_pro_init(double *om0, double *anorm, int *flag)
-{
-    if (threadIdx.x == 0) {
-        om0[0] = 1.0;
-        *anorm = 0.0;
-        flag[0] = flag[1] = flag[2] = 0;
-    }
-}
-
-// beta_k = sqrt(sum of the norm partials of the orthogonalised z (flag set)
-// or of the unorthogonalised z); w_{k+1} := z / beta_k
-__global__ __launch_bounds__(256) void k_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k,
-                                                          int64_t n, const double *normpart, int P,
-                                                          const double *z0part, int P0, const int *flag)
-{
-    __shared__ double sbuf[4];
-    const bool f = *flag != 0;
-    const double b = sqrt(f ? sum_parts(normpart, P, sbuf) : sum_parts(z0part, P0, sbuf));
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) wnext[i] = z[i] / b;
-    if (blockIdx.x == 0 && threadIdx.x == 0) beta[k] = b;
-}
-
-inline int ok() { return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP; }
 
 }  // namespace
+
+int launch_lz_post(double *z, const double *wprev, const double *wk, double *wnext, double *alpha, double *beta,
+                   int64_t k, int64_t n, const double *V, int64_t ldv, const double *omP, const double *omC,
+                   double *omN, double *anorm, int *flag, double *slots, double *cgs, int64_t kcap, LzCtl *ctl,
+                   hipStream_t st)
+{
+    const int P = (int)cdiv(n, PR);
+    if (P > MAXP) return GSYEIG_ETOOBIG;
+    LzStep s{z, wprev, wk, wnext, alpha, beta, k, n, omP, omC, omN, anorm, flag, 0.5 * sqrt((double)n) * 0x1p-53,
+             slots, ctl};
+    hipLaunchKernelGGL(k_lz_step, dim3((unsigned)P), dim3(1024), 0, st, s);
+    if (hipGetLastError() != hipSuccess) return GSYEIG_EHIP;
+    static int grid = 0;
+    if (!grid) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_lz_cgs, 1024, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1, cus = 256;
+        grid = per_cu * cus;
+    }
+    LzCgs c{z, wnext, beta, k, n, V, ldv, flag, cgs, kcap, ctl};
+    hipLaunchKernelGGL(k_lz_cgs, dim3((unsigned)grid), dim3(1024), 0, st, c);
+    return hipGetLastError() == hipSuccess ? 0 : GSYEIG_EHIP;
+}
+
+// buffers launch_lz_post needs, all STAGE_SENTINEL before the first step:
+// the partial-sum slots (lz_post_slots doubles) and the Gram-Schmidt
+// buffers for k + 1 <= kcap (lz_cgs_doubles)
+int lz_post_slots() { return 4 * MAXP; }
+int64_t lz_cgs_doubles(int64_t n, int64_t kcap)
+{
+    return 2 * cdiv(n, TR) * kcap + 2 * kcap + 2 * n + cdiv(n, 64);
+}
 
 int launch_pro_init(double *om0, double *anorm, int *flag, hipStream_t st)
 {
     hipLaunchKernelGGL(k_pro_init, dim3(1), dim3(64), 0, st, om0, anorm, flag);
-    return ok();
-}
-
-int launch_pro_omega(const double *alpha, const double *beta, int64_t k, const double *z0part, int64_t n,
-                     const double *omP, const double *omC, double *omN, double *anorm, int *flag, hipStream_t st)
-{
-    const double eps1 = 0.5 * sqrt((double)n) * 0x1p-53;
-    hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(1024), 0, st, alpha, beta, k, z0part, lz_z0_parts(n), omP, omC,
-                       omN, anorm, flag, eps1);
-    return ok();
-}
-
-int launch_lz_normalize_sel(const double *z, double *wnext, double *beta, int64_t k, int64_t n,
-                            const double *normpart, const double *z0part, const int *flag, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_lz_normalize_sel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, z, wnext, beta, k, n,
-                       normpart, lz_norm_parts(n), z0part, lz_z0_parts(n), flag);
     return ok();
 }
 
