@@ -60,6 +60,23 @@ def measured_traffic(kernel, n, prec):
     return None
 
 
+def sweep_kernels(kind, block=512):
+    """(KI1 kernel, KI3 kernel) of sweep kind `kind` (gsyeig_set_trsv_sweep:
+    0 both work queues, 1 both one workgroup per tile, 2 per-tile KI1 and
+    queue KI3, 3 the reverse); block 64 runs the 64-row chains."""
+    if block == 64:
+        return "k_trsv_n", "k_trsv_t"
+    return ("k_trsvq_n" if kind in (0, 3) else "k_trsv_w_n"), ("k_trsvq_t" if kind in (0, 2) else "k_trsv_w_t")
+
+
+def sweep_traffic(kind, block, n, prec):
+    """Mean measured HBM bytes per launch of the two sweep kernels (None if
+    either has no current counter summary)."""
+    a, b = sweep_kernels(kind, block)
+    ta, tb = measured_traffic(a, n, prec), measured_traffic(b, n, prec)
+    return None if ta is None or tb is None else 0.5 * (ta + tb)
+
+
 def cpu_baseline(n_target, law="spaced", sizes=(768, 1024, 1536, 2048)):
     """The oracle (plain C, FP64) on a bounded sample: full solves of the same
     generator at a few sizes (s = ceil(0.006 n), the config's ratio), a
@@ -190,6 +207,8 @@ def main():
         rc = gs.gsyeig_set_trsv_sweep(solver.ctx, args.trsv_sweep)
         if rc:
             raise gs.GsyeigError("gsyeig_set_trsv_sweep", rc)
+    kind = args.trsv_sweep if args.trsv_sweep >= 0 else (tuning["trsv_sweep"] if tuning else 0)
+    kblock = tuning["trsv_block"] if tuning and args.trsv_sweep < 0 else 512
     opts = gs.gsyeig_opts_default()
     opts.profile_every = args.profile_every
     if args.reorth >= 0:
@@ -289,16 +308,19 @@ def main():
                    "block": int(opts.block), "lanczos_steps": int(last.steps), "reorth": int(opts.reorth),
                    "reorth_steps": int(last.reorth_steps), "parallelism": "single-gpu"},
         "roofline": ({"bound": "hbm", "achieved": sy_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": (sy_gbs / HBM_PEAK_GBS) if sy_gbs else None, "traffic": None,
-                      "kernel": "k_symv_tiles_q + k_symv_reduce (KE's SYMV with C)", "avg_launch_ms": sy_ms,
+                      "frac": (sy_gbs / HBM_PEAK_GBS) if sy_gbs else None,
+                      "traffic": measured_traffic("k_symv_tiles_q", n, "fp64"),
+                      "kernel": "k_symv_tiles_q + k_symv_reduce (KE's SYMV with C; traffic: the tile pass)",
+                      "avg_launch_ms": sy_ms,
                       "algorithmic_bytes_per_launch": tri_bytes + vec_bytes} if ke else
                      {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
-                      "traffic": measured_traffic("k_trsv_w", n, "fp64"),
-                      "kernel": "k_trsv_w_n/k_trsv_w_t (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
-                      "algorithmic_bytes_per_launch": tri_bytes + vec_bytes}),
+                      "traffic": sweep_traffic(kind, kblock, n, "fp64"),
+                      "kernel": "%s/%s (KI1/KI3, mean of the two)" % sweep_kernels(kind, kblock),
+                      "avg_launch_ms": trsv_ms, "algorithmic_bytes_per_launch": tri_bytes + vec_bytes}),
         "kernels": ({"symv_ms": t2, "symv_GBs": symv_gbs, "samples": samples} if ke else
-                    {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_tile_pass_ms": t2,
+                    {"ki1": sweep_kernels(kind, kblock)[0], "ki1_ms": t1, "ki3": sweep_kernels(kind, kblock)[1],
+                     "ki3_ms": t3, "trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_tile_pass_ms": t2,
                      "symv_tile_pass_GBs": symv_gbs, "samples": samples,
                      "note": "KI2 is timed as its tile pass; its reduction runs inside KI3 (trsv_ms)"}),
         "stages_ms": {"gs1": last.t_gs1_ms, "gs2": last.t_gs2_ms, "loop": last.t_ki_ms, "ki5": last.t_ki5_ms,
@@ -723,8 +745,28 @@ def bench_mixed(args, cfg):
     solver = gs.Solver()
     Lam = torch.empty(s, dtype=torch.float64, device=dev)
     X = torch.empty(s, n, dtype=torch.float64, device=dev)
+    kind, kblock, tunings, tuned_for = 0, 512, {}, [None]
+
+    def tune(prec):
+        # the sweep kernels of this precision: autotuned unless pinned by --trsv-sweep
+        nonlocal kind, kblock
+        if tuned_for[0] == prec:
+            return
+        tuned_for[0] = prec
+        if args.trsv_sweep >= 0:
+            rc = gs.gsyeig_set_trsv_sweep(solver.ctx, args.trsv_sweep)
+            if rc:
+                raise gs.GsyeigError("gsyeig_set_trsv_sweep", rc)
+            kind, kblock = args.trsv_sweep, 512
+        elif not args.no_autotune:
+            rc, tu = gs.gsyeig_autotune(solver.ctx, n, prec, args.tune_cache or None)
+            if rc:
+                raise gs.GsyeigError("gsyeig_autotune", rc)
+            tunings["mixed" if prec == gs.GSYEIG_MIXED else "fp64"] = tu.as_dict()
+            kind, kblock = tu.trsv_sweep, tu.trsv_block
 
     def run(prec):
+        tune(prec)
         o = gs.gsyeig_opts_default()
         o.prec = prec
         o.profile_every = args.profile_every
@@ -764,6 +806,7 @@ def bench_mixed(args, cfg):
     e_lam = float(np.max(np.abs(lam_mixed - lam_true)) / mx)
     value = sum(times) / len(times)
     last = infos[-1]
+    kind_m, kblock_m = kind, kblock  # the mixed solves' sweeps (the FP64 comparison may retune)
     fp64 = None
     if not args.no_fp64_compare:
         dt64, inf64 = run(gs.GSYEIG_FP64)
@@ -794,10 +837,12 @@ def bench_mixed(args, cfg):
                    "block_cols": int(last.block_cols), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": trsv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (trsv_gbs / HBM_PEAK_GBS) if trsv_gbs else None,
-                     "traffic": measured_traffic("k_trsv_w", n, "fp32"),
-                     "kernel": "k_trsv_w_n/k_trsv_w_t on FP32 W (KI1/KI3, mean of the two)", "avg_launch_ms": trsv_ms,
+                     "traffic": sweep_traffic(kind_m, kblock_m, n, "fp32"),
+                     "kernel": "%s/%s on FP32 W (KI1/KI3, mean of the two)" % sweep_kernels(kind_m, kblock_m),
+                     "avg_launch_ms": trsv_ms,
                      "algorithmic_bytes_per_launch": tri32 + vec},
-        "kernels": {"trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
+        "kernels": {"ki1": sweep_kernels(kind_m, kblock_m)[0], "ki1_ms": t1, "ki3": sweep_kernels(kind_m, kblock_m)[1],
+                    "ki3_ms": t3, "trsv_ms": trsv_ms, "trsv_GBs": trsv_gbs, "symv_ms": t2, "symv_GBs": symv_gbs,
                     "samples": samples},
         "stages_ms": {"gs1": last.t_gs1_ms, "ki_loop": last.t_ki_ms, "ki5": last.t_ki5_ms, "bt1": last.t_bt1_ms,
                       "refine": last.t_refine_ms, "check": last.t_check_ms, "total": last.t_total_ms},
@@ -807,6 +852,8 @@ def bench_mixed(args, cfg):
                    "pass": bool(e_lam <= 1e-10 and last.eta_max <= 1e-10)},
         "fp64_same_input": fp64,
     }
+    if tunings:
+        out["tuning"] = tunings
     solver.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
