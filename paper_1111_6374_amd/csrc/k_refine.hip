@@ -935,7 +935,7 @@ struct Bump {
     size_t off;
     template <typename T> T *take(size_t count)
     {
-        T *p = (T *)(base + off);
+        T *p = base ? (T *)(base + off) : nullptr;  // base == nullptr: sizes only
         off += (count * sizeof(T) + 255) & ~(size_t)255;
         return p;
     }
