@@ -361,11 +361,11 @@ __device__ double sum_published(const double *slot, int P, LzCtl *ctl, unsigned 
     if (threadIdx.x < 64) {
         const int l = threadIdx.x;
         double acc = 0.0;
-        for (int p0 = 0; p0 < P; p0 += 64 * 16) {
-            unsigned long long v[16];
+        for (int p0 = 0; p0 < P; p0 += 64 * 4) {
+            unsigned long long v[4];
             unsigned live = 0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
+            for (int c = 0; c < 4; ++c) {
                 const int p = p0 + l + 64 * c;
                 live |= (p < P ? 1u : 0u) << c;
                 v[c] = (p < P) ? __hip_atomic_load(reinterpret_cast<const unsigned long long *>(slot + p),
@@ -376,24 +376,24 @@ __device__ double sum_published(const double *slot, int P, LzCtl *ctl, unsigned 
             for (;;) {
                 bool pend = false;
 #pragma unroll
-                for (int c = 0; c < 16; ++c) pend |= ((live >> c) & 1u) && v[c] == STAGE_SENTINEL;
+                for (int c = 0; c < 4; ++c) pend |= ((live >> c) & 1u) && v[c] == STAGE_SENTINEL;
                 if (!__any(pend)) break;
                 if (++it > lim) {
                     __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-                    for (int c = 0; c < 16; ++c)
+                    for (int c = 0; c < 4; ++c)
                         if (v[c] == STAGE_SENTINEL) v[c] = 0ull;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-                for (int c = 0; c < 16; ++c)
+                for (int c = 0; c < 4; ++c)
                     if (((live >> c) & 1u) && v[c] == STAGE_SENTINEL)
                         v[c] = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(slot + p0 + l + 64 * c),
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
+            for (int c = 0; c < 4; ++c)
                 if ((live >> c) & 1u) acc += __longlong_as_double((long long)v[c]);
         }
         acc = wave_sum(acc);
@@ -447,6 +447,22 @@ __global__ __launch_bounds__(1024) void k_lz_step(LzStep a)
     }
     __syncthreads();
     const double bkm1 = s_in[1];
+    // the omega recurrence's inputs for j < OMQ * 1024 (earlier steps' alpha,
+    // beta and omega columns): loaded now, off the path of the two sums
+    constexpr int OMQ = 3;
+    double pb[OMQ], pbm[OMQ], pa[OMQ], pc0[OMQ], pc1[OMQ], pcm[OMQ], pp[OMQ];
+#pragma unroll
+    for (int r = 0; r < OMQ; ++r) {
+        const int64_t j = tid + 1024 * r;
+        const bool in = j < k;
+        pb[r] = in ? a.beta[j] : 0.0;
+        pa[r] = in ? a.alpha[j] : 0.0;
+        pc0[r] = in ? a.omC[j] : 0.0;
+        pc1[r] = in ? a.omC[j + 1] : 0.0;
+        pp[r] = in ? a.omP[j] : 0.0;
+        pbm[r] = (in && j > 0) ? a.beta[j - 1] : 0.0;
+        pcm[r] = (in && j > 0) ? a.omC[j - 1] : 0.0;
+    }
     // z := z - beta_{k-1} w_{k-1}; alpha_k = w_k . z
     double zr[PR / 1024], wr[PR / 1024];
     double d = 0.0;
@@ -480,7 +496,18 @@ __global__ __launch_bounds__(1024) void k_lz_step(LzStep a)
     const double tau = a.eps1 * an;
     const double inv = (bk > 0.0) ? 1.0 / bk : 0.0;
     double mx = 0.0;
-    for (int64_t j = tid; j < k; j += 1024) {
+#pragma unroll
+    for (int r = 0; r < OMQ; ++r) {
+        const int64_t j = tid + 1024 * r;
+        if (j < k) {
+            double num = pb[r] * pc1[r] + (pa[r] - ak) * pc0[r] - bkm1 * pp[r];
+            if (j > 0) num += pbm[r] * pcm[r];
+            const double o = (num + copysign(tau, num)) * inv;
+            if (g == 0) a.omN[j] = o;
+            mx = fmax(mx, fabs(o));
+        }
+    }
+    for (int64_t j = tid + 1024 * OMQ; j < k; j += 1024) {
         double num = a.beta[j] * a.omC[j + 1] + (a.alpha[j] - ak) * a.omC[j] - bkm1 * a.omP[j];
         if (j > 0) num += a.beta[j - 1] * a.omC[j - 1];
         const double o = (num + copysign(tau, num)) * inv;
@@ -594,6 +621,39 @@ __device__ __forceinline__ double poll1(const double *p, bool ok, LzCtl *ctl, un
     return __longlong_as_double((long long)v);
 }
 
+// Up to K published values per lane, base[c * stride] for c < cnt (cnt may
+// differ between lanes; out[c] = 0 beyond it): all loads issued at once,
+// then the sentinels polled again together (bounded, as poll1).  Called by
+// every active lane of the wave.
+template <int K>
+__device__ __forceinline__ void poll_strided(const double *base, int64_t stride, int cnt, double (&out)[K], LzCtl *ctl,
+                                             unsigned lim)
+{
+    unsigned long long v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = (c < cnt) ? ldb(base + c * stride) : 0ull;
+    unsigned it = 0;
+    for (;;) {
+        bool pend = false;
+#pragma unroll
+        for (int c = 0; c < K; ++c) pend |= (c < cnt) && v[c] == STAGE_SENTINEL;
+        if (!__any(pend)) break;
+        if (++it > lim) {
+            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if (v[c] == STAGE_SENTINEL) v[c] = 0ull;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c < cnt && v[c] == STAGE_SENTINEL) v[c] = ldb(base + c * stride);
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) out[c] = __longlong_as_double((long long)v[c]);
+}
+
 __global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
 {
     if (*(volatile const int *)a.flag == 0) return;  // this step does not orthogonalise
@@ -625,10 +685,16 @@ __global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
                 // T: tp[rt][c] = V(rows of rt, c)^T z(rows of rt), TC columns
                 const int64_t rt = d % P.rt, c0 = (d / P.rt) * TC;
                 double zr[TR / 1024];
+                if (pass) {  // z1, published by the previous pass's N items
+                    const int64_t i0 = rt * TR + tid;
+                    const int cnt = (i0 < n) ? (int)((n - i0 + 1023) / 1024) : 0;
+                    poll_strided<TR / 1024>(zin + i0, 1024, cnt < TR / 1024 ? cnt : TR / 1024, zr, ctl, lim);
+                } else {
 #pragma unroll
-                for (int p = 0; p < TR / 1024; ++p) {
-                    const int64_t i = rt * TR + tid + 1024 * p;
-                    zr[p] = (i < n) ? (pass ? poll1(zin + i, true, ctl, lim) : zin[i]) : 0.0;
+                    for (int p = 0; p < TR / 1024; ++p) {
+                        const int64_t i = rt * TR + tid + 1024 * p;
+                        zr[p] = (i < n) ? zin[i] : 0.0;
+                    }
                 }
                 // every load from a clamped in-bounds address (rows beyond n
                 // meet zr = 0; columns beyond kc are never written out)
@@ -657,7 +723,14 @@ __global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
                 const int64_t c = (d - P.nt) * 1024 + tid;
                 if (c < kc) {
                     double s = 0.0;
-                    for (int64_t r = 0; r < P.rt; ++r) s += poll1(tp + r * a.kcap + c, true, ctl, lim);
+                    for (int64_t r0 = 0; r0 < P.rt; r0 += 8) {
+                        double v[8];
+                        const int64_t left = P.rt - r0;
+                        poll_strided<8>(tp + r0 * a.kcap + c, a.kcap, left < 8 ? (int)left : 8, v, ctl, lim);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (q < left) s += v[q];
+                    }
                     publish(hh + c, s);
                 }
             } else {
@@ -671,18 +744,28 @@ __global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
                 const int64_t cs = wv * per, ce = (cs + per < kc) ? cs + per : kc;
                 const double *Vr = a.V + rr;
                 double acc = 0.0;
-                for (int64_t c0 = cs; c0 < ce; c0 += 64) {
-                    const int64_t cn = (ce - c0 < 64) ? ce - c0 : 64;
-                    const double hv = poll1(hh + c0 + lane, lane < cn, ctl, lim);
-                    int u = 0;
-                    for (; u + 8 <= cn; u += 8) {
-                        double v[8];
+                // the wave's coefficients, 8 chunks of 64 columns per poll
+                for (int64_t g0 = cs; g0 < ce; g0 += 8 * 64) {
+                    double hq[8];
+                    const int64_t rem = ce - g0 - lane;
+                    const int cnt = rem > 0 ? (int)((rem + 63) / 64) : 0;
+                    poll_strided<8>(hh + g0 + lane, 64, cnt < 8 ? cnt : 8, hq, ctl, lim);
 #pragma unroll
-                        for (int x = 0; x < 8; ++x) v[x] = Vr[(c0 + u + x) * a.ldv];
+                    for (int q = 0; q < 8; ++q) {
+                        const int64_t c0 = g0 + 64 * q;
+                        if (c0 >= ce) break;
+                        const int64_t cn = (ce - c0 < 64) ? ce - c0 : 64;
+                        const double hv = hq[q];
+                        int u = 0;
+                        for (; u + 8 <= cn; u += 8) {
+                            double v[8];
 #pragma unroll
-                        for (int x = 0; x < 8; ++x) acc = fma(v[x], rdlane(hv, u + x), acc);
+                            for (int x = 0; x < 8; ++x) v[x] = Vr[(c0 + u + x) * a.ldv];
+#pragma unroll
+                            for (int x = 0; x < 8; ++x) acc = fma(v[x], rdlane(hv, u + x), acc);
+                        }
+                        for (; u < cn; ++u) acc = fma(Vr[(c0 + u) * a.ldv], rdlane(hv, u), acc);
                     }
-                    for (; u < cn; ++u) acc = fma(Vr[(c0 + u) * a.ldv], rdlane(hv, u), acc);
                 }
                 s_red[wv][lane] = acc;
                 __syncthreads();
@@ -704,13 +787,24 @@ __global__ __launch_bounds__(1024) void k_lz_cgs(LzCgs a)
         } else {
             // E: beta_k of the orthogonalised z and w_{k+1} = z / beta_k
             double v = 0.0;
-            for (int64_t p = tid; p < P.nn; p += 1024) v += poll1(sb + P.np + p, true, ctl, lim);
+            for (int64_t p0 = 0; p0 < P.nn; p0 += 8 * 1024) {
+                double pv[8];
+                const int64_t rem = P.nn - p0 - tid;
+                const int cnt = rem > 0 ? (int)((rem + 1023) / 1024) : 0;
+                poll_strided<8>(sb + P.np + p0 + tid, 1024, cnt < 8 ? cnt : 8, pv, ctl, lim);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v += pv[c];
+            }
             const double bk = sqrt(bsum1024(v, s16));
             const int64_t e = q - P.e0;
+            double zv[PR / 1024];
+            const int64_t i0 = e * PR + tid;
+            const int cz = (i0 < n) ? (int)((n - i0 + 1023) / 1024) : 0;
+            poll_strided<PR / 1024>(sb + P.z2 + i0, 1024, cz < PR / 1024 ? cz : PR / 1024, zv, ctl, lim);
 #pragma unroll
             for (int p = 0; p < PR / 1024; ++p) {
-                const int64_t i = e * PR + tid + 1024 * p;
-                if (i < n) a.wnext[i] = poll1(sb + P.z2 + i, true, ctl, lim) / bk;
+                const int64_t i = i0 + 1024 * p;
+                if (i < n) a.wnext[i] = zv[p] / bk;
             }
             if (e == 0 && tid == 0) a.beta[k] = bk;
         }
