@@ -132,6 +132,12 @@ typedef struct {
                            /*   bisection and inverse iteration, back-transformed */
                            /*   (Sec. 2.2, TD1-TD3; the dense comparator).  KE    */
                            /*   and TD: FP64, block = 1, invert = 0 only          */
+    int64_t batch_mode;    /* gsyeig_solve_batched only: 0 (default) = the       */
+                           /*   Lanczos phase of every instance it can take      */
+                           /*   (n <= 4096, variant KI, block 1, reorth 2, no    */
+                           /*   v0, invert 0) runs in one launch, one workgroup  */
+                           /*   per instance, largest first; 1 = every instance  */
+                           /*   is a gsyeig_solve on a worker stream              */
 } gsyeig_opts;
 
 typedef struct {
@@ -492,15 +498,33 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
 
 /* Row a10 of the hot path (batched driver; the 3-5 %-of-the-spectrum regime
  * of the paper's conclusions, Sec. 6): `count` independent pencils, each
- * solved exactly as by gsyeig_solve.  All array arguments are HOST arrays of
- * length count holding per-instance sizes and DEVICE pointers (A[i], B[i],
- * Lambda[i], X[i]; same layouts and in-place behaviour as gsyeig_solve).
- * Instances are processed largest first by `nstreams` (1..16) host threads,
- * each with its own worker context and HIP stream owned by `ctx` (created
- * on first use, freed by gsyeig_destroy).  status[i] receives instance i's
- * return code; infos (host, may be NULL) its info.  Synchronises.  Returns
- * 0 if every instance succeeded, else the first nonzero status in index
- * order, or a negative code for an illegal batched argument. */
+ * solved by the method of gsyeig_solve with the same options.  All array
+ * arguments are HOST arrays of length count holding per-instance sizes and
+ * DEVICE pointers (A[i], B[i], Lambda[i], X[i]; same layouts and in-place
+ * behaviour as gsyeig_solve).  Work is spread over `nstreams` (1..16) host
+ * threads, each with its own worker context and HIP stream owned by `ctx`
+ * (created on first use, freed by gsyeig_destroy), largest instance first.
+ * opts->batch_mode 0 (default): the Cholesky factorisation (and, mixed, the
+ * FP32 operator data) of each instance runs on the workers; then ONE launch
+ * runs the Lanczos phase of every instance with n <= 4096 (KI1-KI4 and the
+ * convergence pre-checks of KI5; one workgroup per instance, instances
+ * taken from a device-side queue largest first); then the full convergence
+ * check, the Ritz vectors, BT1, the refinement (mixed) and the check of
+ * each instance run on the workers, an instance whose full check fails
+ * going back to the Lanczos launch for more steps.  Same method, own
+ * summation order: results agree with gsyeig_solve's to within the
+ * convergence tolerance, not bit for bit.  This mode holds every such
+ * instance's factor, basis (n x min(n, max_steps) FP64) and, mixed, FP32
+ * copies of A and U at once in device memory.  Instances it cannot take
+ * (n > 4096, or options other than variant KI, block 1, reorth 2, invert 0,
+ * no v0) are solved as in mode 1 in the same call.  batch_mode 1: every
+ * instance is a gsyeig_solve on a worker (bit for bit equal to it).
+ * status[i] receives instance i's return code; infos (host, may be NULL)
+ * its info (batch_mode 0: t_ki_ms is the instance's time in the shared
+ * launch, t_total_ms the sum of its phases).  Synchronises.  Returns 0 if
+ * every instance succeeded, else the first nonzero status in index order,
+ * or a negative code for an illegal batched argument (-9: batch_mode not
+ * 0 or 1). */
 int gsyeig_solve_batched(gsyeig_ctx *ctx, int64_t count, const int64_t *n, const int64_t *s,
                          const double *const *A, const int64_t *lda, double *const *B,
                          const int64_t *ldb, const gsyeig_opts *opts, double *const *Lambda,

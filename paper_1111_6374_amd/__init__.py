@@ -65,7 +65,8 @@ class gsyeig_opts(ctypes.Structure):
                 ("basis", ctypes.c_int64),
                 ("keep", ctypes.c_int64),
                 ("block_acc32", ctypes.c_int64),
-                ("variant", ctypes.c_int64)]
+                ("variant", ctypes.c_int64),
+                ("batch_mode", ctypes.c_int64)]
 
 
 class gsyeig_info(ctypes.Structure):

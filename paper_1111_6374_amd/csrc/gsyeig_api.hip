@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <numeric>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -447,6 +448,40 @@ static int semiorth_coeffs(gsyeig_ctx *ctx, int64_t n, int64_t m, const double *
     return launch_backsolve(G, m, m, nvec, Dv, S, m, ctx->stream);
 }
 
+// KI5's vectors once theta holds the nvec wanted Ritz values of T_m: S
+// (m x nvec) by inverse iteration, made orthonormal (sequential
+// Gram-Schmidt in clusters if Cholesky QR cannot), R^-1 S for a
+// semi-orthogonal basis (reorth 2), Y = V_m S, theta_out = theta.
+// oinfo_d[2] != 0 afterwards if V_m^T V_m was not positive definite.
+static int lz_ritz_vectors(gsyeig_ctx *ctx, int64_t n, int64_t m, int64_t nvec, int reorth, const double *alpha,
+                           const double *beta, const double *V, int64_t ldv, const double *theta, double *lastc,
+                           double *tri, double *theta_out, double *Y, int64_t ldy, int *oinfo_d)
+{
+    void *p;
+    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)nvec, &p));
+    double *S = (double *)p;
+    int *h = (int *)ctx->host_pinned + 3;
+    TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 0, lastc, ctx->stream));
+    TRY(orthonormalise_cols(ctx, m, nvec, S, m, oinfo_d));
+    HIP_TRY(hipMemcpyAsync(h, oinfo_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (*h != 0) {  // near-parallel vectors or Gram not positive definite: sequential Gram-Schmidt in clusters
+        ctx->n_fallback += 1;
+        ctx->fallback_why = 1;
+        TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
+    }
+    if (reorth == 2) TRY(semiorth_coeffs(ctx, n, m, V, ldv, S, nvec, oinfo_d + 2));
+    else HIP_TRY(hipMemsetAsync(oinfo_d + 2, 0, sizeof(int), ctx->stream));
+    GemmDesc d{};
+    d.m = n; d.n = nvec; d.k = m;
+    d.A = V; d.lda = ldv; d.a_layout = 0;
+    d.B = S; d.ldb = m; d.b_layout = 0;
+    d.C = Y; d.ldc = ldy; d.c_layout = 0;
+    d.alpha = 1.0; d.beta = 0.0;
+    TRY(launch_gemm_f64(d, ctx->stream));
+    return launch_copy(theta, theta_out, nvec, ctx->stream);
+}
+
 struct LzBufs {
     double *z, *tmp, *red, *red2, *h, *normpart, *z0part;
     int *flag;       // [0] Gram-Schmidt pass needed, [1] count of such steps, [2] next step forced (device)
@@ -636,29 +671,9 @@ static int lz_solve_body(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t nvec, co
         TRY(launch_tri_bisect(alpha, beta, m, nvec, o->which, theta, ctx->stream));
     }
     HIP_TRY(hipEventRecord(ctx->ev[7], ctx->stream));
-    // Ritz vectors: S (m x nvec) by inverse iteration, Y = V_m S
-    TRY(ws_get(ctx, WS_S, sizeof(double) * (size_t)m * (size_t)nvec, &p));
-    double *S = (double *)p;
-    TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 0, lastc, ctx->stream));
     int *oinfo_d = (int *)ctx->dscal + 24;
-    TRY(orthonormalise_cols(ctx, m, nvec, S, m, oinfo_d));
-    HIP_TRY(hipMemcpyAsync(nconv_h, oinfo_d, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (*nconv_h != 0) {  // near-parallel vectors or Gram not positive definite: sequential Gram-Schmidt in clusters
-        ctx->n_fallback += 1;
-        ctx->fallback_why = 1;
-        TRY(launch_tri_vectors(alpha, beta, m, nvec, theta, S, m, tri, 1, lastc, ctx->stream));
-    }
-    if (b.reorth == 2) TRY(semiorth_coeffs(ctx, n, m, V, ldv, S, nvec, oinfo_d + 2));
-    else HIP_TRY(hipMemsetAsync(oinfo_d + 2, 0, sizeof(int), ctx->stream));
-    GemmDesc d{};
-    d.m = n; d.n = nvec; d.k = m;
-    d.A = V; d.lda = ldv; d.a_layout = 0;
-    d.B = S; d.ldb = m; d.b_layout = 0;
-    d.C = Y; d.ldc = ldy; d.c_layout = 0;
-    d.alpha = 1.0; d.beta = 0.0;
-    TRY(launch_gemm_f64(d, ctx->stream));
-    TRY(launch_copy(theta, theta_out, nvec, ctx->stream));
+    TRY(lz_ritz_vectors(ctx, n, m, nvec, b.reorth, alpha, beta, V, ldv, theta, lastc, tri, theta_out, Y, ldy,
+                        oinfo_d));
     HIP_TRY(hipMemcpyAsync(nconv_h + 1, b.flag + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipMemcpyAsync(nconv_h + 2, oinfo_d + 2, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
@@ -875,6 +890,60 @@ static int mixed_operator(gsyeig_ctx *ctx, int64_t n, const double *A, int64_t l
     return 0;
 }
 
+// Mixed mode after the Lanczos phase (k = s + guard Ritz vectors in Y):
+// X0 = U~^-1 Y, the FP64 refinement on (A, B), the FP64 check.  Fills inf
+// except t_gs1_ms and t_total_ms; 0, GSYEIG_ENOCONV, or an error.
+static int mixed_finish(gsyeig_ctx *ctx, int64_t n, int64_t s, int64_t k, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, const gsyeig_opts &o, const float *U32, int64_t ld32,
+                        const double *Dinv, const double *sb, const float *A32, double *Y, int64_t ldy,
+                        const LzResult &r, const BlzResult &br, double *Lambda, double *X, int64_t ldx,
+                        gsyeig_info &inf)
+{
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    TRY(launch_backsolve_f32(U32, ld32, n, k, Dinv, Y, ldy, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
+    RefineOp rop{U32, ld32, sb, A32, ld32};
+    RefineCfg cfg{o.eta_tol, o.refine_iters, o.refine_inner};
+    RefineStats rs{};
+    TRY(refine_run(ctx, n, s, k, o.which, A, lda, B, ldb, rop, cfg, Lambda, X, ldx, &rs));
+    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
+    double *res_d = (double *)ctx->dscal + 64;
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, nullptr, Lambda, X, ldx, res_d));
+    HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
+    double *h = (double *)ctx->host_pinned;
+    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    inf.eta_max = h[0];
+    inf.rho_f = h[1];
+    inf.omega = h[2];
+    inf.normA_f = h[3];
+    inf.normB_f = h[4];
+    float t;
+    inf.t_ki_ms = r.t_loop_ms;
+    inf.t_ki5_ms = r.t_ritz_ms;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_refine_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5])); inf.t_check_ms = t;
+    inf.steps = r.steps;
+    inf.converged = (r.nconv >= s) ? rs.nconv : std::min<int64_t>(r.nconv, rs.nconv);
+    inf.prof_samples = ctx->prof_samples;
+    inf.t_ki1_ms_sum = ctx->prof_ms[0];
+    inf.t_ki2_ms_sum = ctx->prof_ms[1];
+    inf.t_ki3_ms_sum = ctx->prof_ms[2];
+    inf.eta_phase1 = rs.eta0;
+    inf.refine_iters = rs.iters;
+    inf.block_applies = rs.block_applies;
+    inf.block_cols = rs.kept;
+    inf.restarts = br.restarts;
+    inf.basis = br.basis;
+    inf.kept = br.keep;
+    inf.t_rr_ms = br.t_rr_ms;
+    inf.rr_count = br.rr_count;
+    inf.reorth_steps = r.reorth_steps;
+    return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
+}
+
 // Mixed mode of gsyeig_solve: GS1 with FP32 trailing updates, Lanczos with
 // FP32 sweeps (FP64 vectors, alpha/beta, CGS2, T), Ritz vectors for s +
 // guard pairs, X0 = U~^-1 Y, FP64 refinement on (A, B), FP64 check.  B is
@@ -934,18 +1003,33 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
             return GSYEIG_ENOCONV;
         }
     }
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+    inf.t_gs1_ms = t;
+    const int rc = mixed_finish(ctx, n, s, k, A, lda, B, ldb, o, U32, ld32, Dinv, op.sb, op.A32, Y, ldy, r, br,
+                                Lambda, X, ldx, inf);
+    if (rc && rc != GSYEIG_ENOCONV) return rc;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[5]));
+    inf.t_total_ms = t;
+    if (info) *info = inf;
+    return rc;
+}
+
+// FP64 mode after the Lanczos phase (the s Ritz vectors Y in X): X = U^-1 Y,
+// the sign convention, the FP64 check (bdiag: B's diagonal before the
+// factorisation overwrote it).  Fills inf except t_gs1_ms, t_gs2_ms and
+// t_total_ms.
+static int fp64_finish(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, const double *bdiag, const double *Dinv, double *Lambda, double *X, int64_t ldx,
+                       const LzResult &r, const BlzResult &br, gsyeig_info &inf)
+{
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
-    TRY(launch_backsolve_f32(U32, ld32, n, k, Dinv, Y, ldy, ctx->stream));
-    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
-    RefineOp rop{U32, ld32, op.sb, op.A32, ld32};
-    RefineCfg cfg{o.eta_tol, o.refine_iters, o.refine_inner};
-    RefineStats rs{};
-    TRY(refine_run(ctx, n, s, k, o.which, A, lda, B, ldb, rop, cfg, Lambda, X, ldx, &rs));
+    TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
     TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
-    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
     double *res_d = (double *)ctx->dscal + 64;
-    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, nullptr, Lambda, X, ldx, res_d));
-    HIP_TRY(hipEventRecord(ctx->ev[5], ctx->stream));
+    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, bdiag, Lambda, X, ldx, res_d));
+    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
     double *h = (double *)ctx->host_pinned;
     HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -955,31 +1039,25 @@ static int solve_mixed(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, i
     inf.normA_f = h[3];
     inf.normB_f = h[4];
     float t;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
     inf.t_ki_ms = r.t_loop_ms;
     inf.t_ki5_ms = r.t_ritz_ms;
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_refine_ms = t;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5])); inf.t_check_ms = t;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[5])); inf.t_total_ms = t;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_check_ms = t;
     inf.steps = r.steps;
-    inf.converged = (r.nconv >= s) ? rs.nconv : std::min<int64_t>(r.nconv, rs.nconv);
+    inf.converged = r.nconv;
     inf.prof_samples = ctx->prof_samples;
     inf.t_ki1_ms_sum = ctx->prof_ms[0];
     inf.t_ki2_ms_sum = ctx->prof_ms[1];
     inf.t_ki3_ms_sum = ctx->prof_ms[2];
-    inf.eta_phase1 = rs.eta0;
-    inf.refine_iters = rs.iters;
-    inf.block_applies = rs.block_applies;
-    inf.block_cols = rs.kept;
     inf.restarts = br.restarts;
     inf.basis = br.basis;
     inf.kept = br.keep;
     inf.t_rr_ms = br.t_rr_ms;
     inf.rr_count = br.rr_count;
     inf.reorth_steps = r.reorth_steps;
-    if (info) *info = inf;
-    return (r.nconv >= s && rs.eta <= o.eta_tol) ? 0 : GSYEIG_ENOCONV;
+    inf.cluster_fallbacks = ctx->n_fallback;
+    inf.fallback_reason = ctx->fallback_why;
+    return 0;
 }
 
 extern "C" int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
@@ -1049,6 +1127,371 @@ static int solve_inverted(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A
 }
 
 // ------------------------------------------------------------------ C ABI
+// ------------------------------------------------------------------ batch
+// Worker contexts of the batched solves (own streams), created once and
+// kept by the parent context.
+static int ensure_workers(gsyeig_ctx *ctx, int64_t nstreams)
+{
+    while (ctx->nworkers < nstreams) {
+        hipStream_t st;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        gsyeig_ctx *w = nullptr;
+        int rc = gsyeig_create(&w, st);
+        if (rc) {
+            (void)hipStreamDestroy(st);
+            return rc;
+        }
+        ctx->wstreams[ctx->nworkers] = st;
+        ctx->workers[ctx->nworkers++] = w;
+    }
+    return 0;
+}
+
+// f(worker, k) for k < count on nstreams host threads, each driving one
+// worker context; items are taken in order.  Returns the first nonzero f
+// result (the remaining items still run).
+template <typename F>
+static int run_workers(gsyeig_ctx *ctx, int64_t nstreams, int64_t count, F f)
+{
+    std::atomic<int64_t> next(0);
+    std::atomic<int> err(0);
+    auto work = [&](int wi) {
+        gsyeig_ctx *w = ctx->workers[wi];
+        w->trsv_block = ctx->trsv_block;
+        w->trsv_sweep = ctx->trsv_sweep;
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            int z = 0;
+            err.compare_exchange_strong(z, GSYEIG_EHIP);
+            return;
+        }
+        for (;;) {
+            const int64_t k = next.fetch_add(1);
+            if (k >= count) break;
+            const int rc = f(w, k);
+            if (rc) {
+                int z = 0;
+                err.compare_exchange_strong(z, rc);
+            }
+        }
+    };
+    const int nt = (int)std::min<int64_t>(nstreams, count);
+    std::vector<std::thread> th;
+    for (int wi = 0; wi < nt; ++wi) th.emplace_back(work, wi);
+    for (auto &t : th) t.join();
+    return err.load();
+}
+
+static bool batch_lz_eligible(int64_t n, int64_t s, int64_t lda, int64_t ldb, int64_t ldx, const gsyeig_opts &o)
+{
+    if (n < 1 || n > LZB_NMAX || s < 1 || s > n || lda < n || ldb < n || ldx < n) return false;
+    if (o.block != 1 || o.invert || o.variant != GSYEIG_KI || o.reorth != 2 || o.v0) return false;
+    if (o.prec != GSYEIG_FP64 && o.prec != GSYEIG_MIXED) return false;
+    return o.prec == GSYEIG_FP64 || mixed_block(n, s, &o) >= s;
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Row stride of the batch pool's matrices: whole 64-element blocks, moved
+// off multiples of 512 elements, whose rows would all start in the same
+// HBM channel (the kernel reads eight rows of a column group at once).
+static int64_t batch_ld(int64_t n)
+{
+    const int64_t ld = round_ld(n);
+    return (ld % 512 == 0) ? ld + 64 : ld;
+}
+
+// The batched Lanczos kernel reads rows with 16-byte loads that may run past
+// column n - 1 into the row's padding: a caller's FP64 matrix is read in
+// place when its base is 16-byte aligned, rows are an even number of
+// doubles (not a multiple of 512) and n is even; otherwise from a copy.
+static bool aligned16(const double *p, int64_t ld, int64_t n)
+{
+    return ((uintptr_t)p % 16 == 0) && (ld % 2 == 0) && (ld % 512 != 0) && (n % 2 == 0);
+}
+
+// One instance's device data in the batch pool.
+struct BatchInst {
+    int64_t i;                   // index in the caller's arrays
+    int64_t nvec, mmax, ldv, ldom, ld32;
+    double *Dinv;                // inverses of the factor's 64 x 64 diagonal blocks
+    float *U32, *A32;            // mixed: FP32 factor and A
+    double *sb;                  // mixed: super-block inverses of U~ (refinement)
+    double *bdiag;               // FP64: B's diagonal before the factorisation
+    double *Ucp, *Acp;           // FP64: 16-byte aligned copies of U and A (if theirs are not)
+    double *V, *alpha, *beta, *om, *chk;
+    float t_gs1_ms;
+    int gs1;                     // 0, or the leading minor of B that is not positive definite
+};
+
+// An instance whose one-launch Lanczos phase gave no valid Ritz pairs
+// (its basis lost orthogonality, or it reached the step cap) is solved again
+// by the per-instance path on worker w: mixed mode from (A, B) as
+// gsyeig_solve does (B is untouched); FP64 mode from the factor already in
+// B and Dinv (B was overwritten by it).  Returns the instance's code.
+static int batch_resolve(gsyeig_ctx *w, int64_t n, int64_t s, const double *A, int64_t lda, double *B,
+                         int64_t ldb, const gsyeig_opts &o, double *Dinv, const double *bdiag, double *Lambda,
+                         double *X, int64_t ldx, gsyeig_info &inf)
+{
+    memset(&inf, 0, sizeof(inf));
+    if (o.prec == GSYEIG_MIXED) return gsyeig_solve(w, n, s, A, lda, B, ldb, &o, Lambda, X, ldx, &inf);
+    w->n_fallback = w->fallback_why = 0;
+    HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+    TRY(prepare_solves(w, n, B, ldb, Dinv));
+    LzResult r{};
+    const int lrc = lz_solve(w, n, s, s, op_fp64(A, lda, B, ldb, Dinv), &o, Lambda, X, ldx, &r);
+    if (lrc && lrc != GSYEIG_ENOCONV) return lrc;
+    BlzResult br{};
+    TRY(fp64_finish(w, n, s, A, lda, B, ldb, bdiag, Dinv, Lambda, X, ldx, r, br, inf));
+    float t;
+    HIP_TRY(hipEventElapsedTime(&t, w->ev[0], w->ev[4]));
+    inf.t_total_ms = t;
+    return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
+}
+
+// The batched solve (batch_mode 0) of the instances idx (largest first):
+// GS1 and the operator data of each on the worker streams; the Lanczos
+// phase of all of them in one launch of k_lzb (one workgroup per instance,
+// largest first from a device-side queue, each running until its
+// convergence pre-check passes); the full convergence check, KI5, BT1 and
+// (mixed) the refinement and the check of each on the workers.  An instance
+// whose full check fails goes back to the Lanczos kernel for more steps.
+static int solve_batched_lz(gsyeig_ctx *ctx, const std::vector<int64_t> &idx, const int64_t *n, const int64_t *s,
+                            const double *const *A, const int64_t *lda, double *const *B, const int64_t *ldb,
+                            const gsyeig_opts &o, double *const *Lambda, double *const *X, const int64_t *ldx,
+                            int64_t nstreams, int *status, gsyeig_info *infos)
+{
+    const bool mixed = o.prec == GSYEIG_MIXED;
+    const int64_t cnt = (int64_t)idx.size();
+    std::vector<BatchInst> bi(cnt);
+    size_t total = al256(sizeof(LzbDesc) * cnt) + al256(sizeof(int) * cnt) + 256;
+    for (int64_t j = 0; j < cnt; ++j) {
+        BatchInst &b = bi[j];
+        const int64_t i = idx[j], nn = n[i];
+        b.i = i;
+        b.nvec = mixed ? mixed_block(nn, s[i], &o) : s[i];
+        b.mmax = std::max<int64_t>(eff_max_steps(nn, s[i], &o), std::min<int64_t>(b.nvec, nn));
+        b.ldv = round_ld(nn);
+        b.ldom = b.mmax + 8;
+        b.ld32 = batch_ld(nn);
+        total += al256(tri_aux_bytes(nn)) + al256(sizeof(double) * (size_t)b.ldv * (size_t)(b.mmax + 1)) +
+                 2 * al256(sizeof(double) * (size_t)b.mmax) + al256(sizeof(double) * (size_t)(3 * b.ldom + 8)) +
+                 al256(sizeof(double) * (size_t)lzb_scratch_doubles(nn, b.mmax));
+        if (mixed)
+            total += 2 * al256(sizeof(float) * (size_t)b.ld32 * (size_t)nn) + al256(trsv_w_side_bytes(nn));
+        else
+            total += al256(sizeof(double) * (size_t)nn) +
+                     (aligned16(B[i], ldb[i], nn) ? 0 : al256(sizeof(double) * (size_t)b.ld32 * (size_t)nn)) +
+                     (aligned16(A[i], lda[i], nn) ? 0 : al256(sizeof(double) * (size_t)b.ld32 * (size_t)nn));
+    }
+    void *pool;
+    TRY(ws_get(ctx, WS_BATCH, total, &pool));
+    char *cur = (char *)pool;
+    auto take = [&](size_t bytes) {
+        char *p = cur;
+        cur += al256(bytes);
+        return p;
+    };
+    LzbDesc *desc_d = (LzbDesc *)take(sizeof(LzbDesc) * cnt);
+    int *order_d = (int *)take(sizeof(int) * cnt);
+    unsigned *next_d = (unsigned *)take(256);
+    for (int64_t j = 0; j < cnt; ++j) {
+        BatchInst &b = bi[j];
+        const int64_t nn = n[b.i];
+        b.Dinv = (double *)take(tri_aux_bytes(nn));
+        b.V = (double *)take(sizeof(double) * (size_t)b.ldv * (size_t)(b.mmax + 1));
+        b.alpha = (double *)take(sizeof(double) * (size_t)b.mmax);
+        b.beta = (double *)take(sizeof(double) * (size_t)b.mmax);
+        b.om = (double *)take(sizeof(double) * (size_t)(3 * b.ldom + 8));
+        b.chk = (double *)take(sizeof(double) * (size_t)lzb_scratch_doubles(nn, b.mmax));
+        b.U32 = b.A32 = nullptr;
+        b.sb = b.bdiag = b.Ucp = b.Acp = nullptr;
+        if (mixed) {
+            b.U32 = (float *)take(sizeof(float) * (size_t)b.ld32 * (size_t)nn);
+            b.A32 = (float *)take(sizeof(float) * (size_t)b.ld32 * (size_t)nn);
+            b.sb = (double *)take(trsv_w_side_bytes(nn));
+        } else {
+            b.bdiag = (double *)take(sizeof(double) * (size_t)nn);
+            if (!aligned16(B[b.i], ldb[b.i], nn)) b.Ucp = (double *)take(sizeof(double) * (size_t)b.ld32 * (size_t)nn);
+            if (!aligned16(A[b.i], lda[b.i], nn)) b.Acp = (double *)take(sizeof(double) * (size_t)b.ld32 * (size_t)nn);
+        }
+    }
+
+    // GS1 and the operator data, each instance on a worker stream
+    TRY(run_workers(ctx, nstreams, cnt, [&](gsyeig_ctx *w, int64_t j) {
+        BatchInst &b = bi[j];
+        const int64_t i = b.i, nn = n[i];
+        int *info_d = (int *)w->dscal + 16;
+        HIP_TRY(hipEventRecord(w->ev[0], w->stream));
+        if (mixed) {
+            // the kernel's row sums read U~'s row padding: zero
+            HIP_TRY(hipMemsetAsync(b.U32, 0, sizeof(float) * (size_t)b.ld32 * (size_t)nn, w->stream));
+            TRY(potrf_mixed_enqueue(w, nn, B[i], ldb[i], b.U32, b.ld32, b.Dinv, info_d));
+            TRY(launch_to_f32(A[i], lda[i], b.A32, b.ld32, nn, nn, w->stream));
+            const int64_t SB = trsv_sb_rows();
+            TRY(launch_sb_inverses_f32(b.U32, b.ld32, nn, b.Dinv, b.sb, b.sb + cdiv(nn, SB) * SB * SB, w->stream));
+        } else {
+            TRY(launch_copy_diag(B[i], ldb[i], nn, b.bdiag, w->stream));
+            TRY(potrf_core(w, nn, B[i], ldb[i], b.Dinv, info_d));
+            if (b.Ucp) {
+                HIP_TRY(hipMemsetAsync(b.Ucp, 0, sizeof(double) * (size_t)b.ld32 * (size_t)nn, w->stream));
+                TRY(launch_blk_copy(B[i], ldb[i], b.Ucp, b.ld32, nn, nn, w->stream));
+            }
+            if (b.Acp) TRY(launch_blk_copy(A[i], lda[i], b.Acp, b.ld32, nn, nn, w->stream));
+        }
+        HIP_TRY(hipEventRecord(w->ev[1], w->stream));
+        int *hi = (int *)w->host_pinned;
+        HIP_TRY(hipMemcpyAsync(hi, info_d, sizeof(int), hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        b.gs1 = hi[0];
+        HIP_TRY(hipEventElapsedTime(&b.t_gs1_ms, w->ev[0], w->ev[1]));
+        return 0;
+    }));
+
+    std::vector<LzbDesc> desc(cnt);
+    std::vector<int> pend;
+    for (int64_t j = 0; j < cnt; ++j) {
+        const BatchInst &b = bi[j];
+        const int64_t i = b.i;
+        if (b.gs1) {
+            status[i] = b.gs1;
+            continue;
+        }
+        LzbDesc &d = desc[j];
+        memset(&d, 0, sizeof(d));
+        d.n = n[i];
+        d.s = s[i];
+        d.nvec = b.nvec;
+        d.mmax = b.mmax;
+        d.every = std::max<int64_t>(1, o.check_every);
+        d.which = o.which;
+        d.tol = o.tol;
+        d.U = mixed ? (const void *)b.U32 : b.Ucp ? (const void *)b.Ucp : (const void *)B[i];
+        d.ldu = (mixed || b.Ucp) ? b.ld32 : ldb[i];
+        d.Dinv = b.Dinv;
+        d.A = mixed ? (const void *)b.A32 : b.Acp ? (const void *)b.Acp : (const void *)A[i];
+        d.lda = (mixed || b.Acp) ? b.ld32 : lda[i];
+        d.seed = o.seed;
+        d.V = b.V;
+        d.ldv = b.ldv;
+        d.alpha = b.alpha;
+        d.beta = b.beta;
+        d.om = b.om;
+        d.ldom = b.ldom;
+        d.chk = b.chk;
+        d.next_check = d.every;
+        d.prev_m = -1;
+        pend.push_back((int)j);
+    }
+    while (!pend.empty()) {
+        // the Lanczos phase of every pending instance: one launch
+        HIP_TRY(hipMemcpyAsync(desc_d, desc.data(), sizeof(LzbDesc) * cnt, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(order_d, pend.data(), sizeof(int) * pend.size(), hipMemcpyHostToDevice,
+                               ctx->stream));
+        TRY(launch_lzb(desc_d, order_d, (int)pend.size(), next_d, mixed ? 1 : 0, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(desc.data(), desc_d, sizeof(LzbDesc) * cnt, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        // full check, KI5, BT1, refinement and check on the workers
+        std::mutex mu;
+        std::vector<int> again;
+        TRY(run_workers(ctx, nstreams, (int64_t)pend.size(), [&](gsyeig_ctx *w, int64_t k) {
+            const int j = pend[k];
+            const BatchInst &b = bi[j];
+            LzbDesc &d = desc[j];
+            const int64_t i = b.i, nn = n[i], m = d.k, nvec = b.nvec;
+            void *p;
+            TRY(ws_get(w, WS_T, sizeof(double) * (size_t)(2 * nvec + 16), &p));
+            double *theta = (double *)p, *lastc = theta + nvec + 1;
+            TRY(ws_get(w, WS_TRI, sizeof(double) * (size_t)nvec * 7 * (size_t)m, &p));
+            double *tri = (double *)p;
+            int *hi = (int *)w->host_pinned;
+            const float t_lz = (float)((double)d.ticks * 1e-5);
+            auto resolve = [&]() {
+                gsyeig_info inf;
+                const int rc = batch_resolve(w, nn, s[i], A[i], lda[i], B[i], ldb[i], o, b.Dinv, b.bdiag, Lambda[i],
+                                             X[i], ldx[i], inf);
+                inf.t_gs1_ms += b.t_gs1_ms;
+                inf.t_ki_ms += t_lz;  // the abandoned one-launch phase counts too
+                inf.t_total_ms += b.t_gs1_ms + t_lz;
+                status[i] = rc;
+                if (infos) infos[i] = inf;
+                return (rc > 0 || rc == GSYEIG_ENOCONV) ? 0 : rc;
+            };
+            if (d.status == 4) return resolve();
+            int64_t nconv = s[i];
+            bool have_theta = false;
+            HIP_TRY(hipEventRecord(w->ev[6], w->stream));
+            if (d.status != 1) {
+                const int64_t w0 = o.which ? nvec - s[i] : 0;
+                int *nconv_d = (int *)w->dscal;
+                TRY(launch_tri_bisect(b.alpha, b.beta, m, nvec, o.which, theta, w->stream));
+                TRY(launch_tri_vectors(b.alpha, b.beta, m, nvec, theta, nullptr, 0, tri, 0, lastc, w->stream));
+                TRY(launch_conv_count(theta, lastc, b.beta + (m - 1), nvec, w0, s[i], 0, o.tol, nconv_d, w->stream));
+                HIP_TRY(hipMemcpyAsync(hi, nconv_d, sizeof(int), hipMemcpyDeviceToHost, w->stream));
+                HIP_TRY(hipStreamSynchronize(w->stream));
+                nconv = hi[0];
+                have_theta = true;
+                if (nconv < s[i] && m < b.mmax) {  // more steps
+                    d.status = 0;
+                    d.next_check = m + d.every;
+                    std::lock_guard<std::mutex> g(mu);
+                    again.push_back(j);
+                    return 0;
+                }
+            }
+            if (!have_theta) TRY(launch_tri_bisect(b.alpha, b.beta, m, nvec, o.which, theta, w->stream));
+            w->n_fallback = w->fallback_why = 0;
+            double *Y, *theta_out;
+            int64_t ldy;
+            if (mixed) {
+                TRY(refine_x0(w, nn, nvec, &Y, &ldy));
+                TRY(ws_get(w, WS_BDIAG, sizeof(double) * (size_t)(nn + 8), &p));
+                theta_out = (double *)p;
+            } else {
+                Y = X[i];
+                ldy = ldx[i];
+                theta_out = Lambda[i];
+            }
+            int *oinfo_d = (int *)w->dscal + 24;
+            TRY(lz_ritz_vectors(w, nn, m, nvec, 2, b.alpha, b.beta, b.V, b.ldv, theta, lastc, tri, theta_out, Y, ldy,
+                                oinfo_d));
+            HIP_TRY(hipEventRecord(w->ev[7], w->stream));
+            HIP_TRY(hipMemcpyAsync(hi + 2, oinfo_d + 2, sizeof(int), hipMemcpyDeviceToHost, w->stream));
+            HIP_TRY(hipStreamSynchronize(w->stream));
+            LzResult r{};
+            r.steps = m;
+            r.nconv = (hi[2] != 0) ? 0 : nconv;  // a basis that lost semi-orthogonality gives no valid vectors
+            r.reorth_steps = d.reorth_steps;
+            r.t_loop_ms = (float)((double)d.ticks * 1e-5);
+            HIP_TRY(hipEventElapsedTime(&r.t_ritz_ms, w->ev[6], w->ev[7]));
+            gsyeig_info inf;
+            memset(&inf, 0, sizeof(inf));
+            BlzResult br{};
+            int rc;
+            if (hi[2] != 0 || nconv < s[i]) {
+                return resolve();
+            } else if (mixed) {
+                rc = mixed_finish(w, nn, s[i], nvec, A[i], lda[i], B[i], ldb[i], o, b.U32, b.ld32, b.Dinv, b.sb,
+                                  b.A32, Y, ldy, r, br, Lambda[i], X[i], ldx[i], inf);
+                if (rc && rc != GSYEIG_ENOCONV) return rc;
+            } else {
+                TRY(fp64_finish(w, nn, s[i], A[i], lda[i], B[i], ldb[i], b.bdiag, b.Dinv, Lambda[i], X[i], ldx[i], r,
+                                br, inf));
+                rc = (r.nconv >= s[i]) ? 0 : GSYEIG_ENOCONV;
+            }
+            inf.t_gs1_ms = b.t_gs1_ms;
+            inf.t_total_ms = inf.t_gs1_ms + inf.t_ki_ms + inf.t_ki5_ms + inf.t_bt1_ms + inf.t_refine_ms + inf.t_check_ms;
+            inf.cluster_fallbacks = w->n_fallback;
+            inf.fallback_reason = w->fallback_why;
+            status[i] = rc;
+            if (infos) infos[i] = inf;
+            return 0;
+        }));
+        std::sort(again.begin(), again.end());
+        pend.swap(again);
+    }
+    return 0;
+}
+
 extern "C" {
 
 const char *gsyeig_version(void) { return "gsyeig-gfx950 0.1.0"; }
@@ -1674,43 +2117,11 @@ int gsyeig_solve(gsyeig_ctx *ctx, int64_t n, int64_t s, const double *A, int64_t
         const int lrc = lz_solve(ctx, n, s, s, lop, &o, Lambda, X, ldx, &r);
         if (lrc && lrc != GSYEIG_ENOCONV) return lrc;  // ENOCONV: finish, report in info
     }
-    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
-    TRY(launch_backsolve(B, ldb, n, s, Dinv, X, ldx, ctx->stream));
-    TRY(launch_sign_normalise(X, ldx, n, s, ctx->stream));
-    HIP_TRY(hipEventRecord(ctx->ev[3], ctx->stream));
-    double *res_d = (double *)ctx->dscal + 64;
-    TRY(check_enqueue(ctx, n, s, A, lda, B, ldb, bdiag, Lambda, X, ldx, res_d));
-    HIP_TRY(hipEventRecord(ctx->ev[4], ctx->stream));
-    double *h = (double *)ctx->host_pinned;
-    HIP_TRY(hipMemcpyAsync(h, res_d, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    inf.eta_max = h[0];
-    inf.rho_f = h[1];
-    inf.omega = h[2];
-    inf.normA_f = h[3];
-    inf.normB_f = h[4];
     float t;
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1])); inf.t_gs1_ms = t;
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[8])); inf.t_gs2_ms = t;
-    inf.t_ki_ms = r.t_loop_ms;
-    inf.t_ki5_ms = r.t_ritz_ms;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3])); inf.t_bt1_ms = t;
-    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4])); inf.t_check_ms = t;
+    TRY(fp64_finish(ctx, n, s, A, lda, B, ldb, bdiag, Dinv, Lambda, X, ldx, r, br, inf));
     HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[4])); inf.t_total_ms = t;
-    inf.steps = r.steps;
-    inf.converged = r.nconv;
-    inf.prof_samples = ctx->prof_samples;
-    inf.t_ki1_ms_sum = ctx->prof_ms[0];
-    inf.t_ki2_ms_sum = ctx->prof_ms[1];
-    inf.t_ki3_ms_sum = ctx->prof_ms[2];
-    inf.restarts = br.restarts;
-    inf.basis = br.basis;
-    inf.kept = br.keep;
-    inf.t_rr_ms = br.t_rr_ms;
-    inf.rr_count = br.rr_count;
-    inf.reorth_steps = r.reorth_steps;
-    inf.cluster_fallbacks = ctx->n_fallback;
-    inf.fallback_reason = ctx->fallback_why;
     if (info) *info = inf;
     return (r.nconv >= s) ? 0 : GSYEIG_ENOCONV;
 }
@@ -1932,42 +2343,34 @@ int gsyeig_solve_batched(gsyeig_ctx *ctx, int64_t count, const int64_t *n, const
     if (!ldx) return -12;
     if (nstreams < 1 || nstreams > GSYEIG_MAX_STREAMS) return -13;
     if (!status) return -14;
-    // worker contexts, created once and kept by the parent context
+    gsyeig_opts o;
+    if (opts) o = *opts; else opts_fill_defaults(&o);
+    if (o.batch_mode != 0 && o.batch_mode != 1) return -9;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    while (ctx->nworkers < nstreams) {
-        hipStream_t st;
-        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        gsyeig_ctx *w = nullptr;
-        int rc = gsyeig_create(&w, st);
-        if (rc) {
-            (void)hipStreamDestroy(st);
-            return rc;
-        }
-        ctx->wstreams[ctx->nworkers] = st;
-        ctx->workers[ctx->nworkers++] = w;
-    }
-    std::vector<int64_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return n[a] > n[b]; });
-    std::atomic<int64_t> next(0);
-    auto work = [&](int wi) {
-        gsyeig_ctx *w = ctx->workers[wi];
-        w->trsv_block = ctx->trsv_block;
-        if (hipSetDevice(ctx->device) != hipSuccess) return;
-        for (;;) {
-            const int64_t k = next.fetch_add(1);
-            if (k >= count) break;
-            const int64_t i = order[k];
-            gsyeig_info inf;
-            status[i] = gsyeig_solve(w, n[i], s[i], A[i], lda[i], B[i], ldb[i], opts, Lambda[i], X[i],
-                                     ldx[i], &inf);
-            if (infos) infos[i] = inf;
-        }
-    };
+    TRY(ensure_workers(ctx, nstreams));
     for (int64_t i = 0; i < count; ++i) status[i] = GSYEIG_EHIP;
-    std::vector<std::thread> th;
-    for (int wi = 0; wi < (int)nstreams; ++wi) th.emplace_back(work, wi);
-    for (auto &t : th) t.join();
+    // the instances the one-launch Lanczos phase takes, and the others
+    std::vector<int64_t> lz, rest;
+    for (int64_t i = 0; i < count; ++i) {
+        const bool ok = o.batch_mode == 0 && batch_lz_eligible(n[i], s[i], lda[i], ldb[i], ldx[i], o) &&
+                        A[i] && B[i] && Lambda[i] && X[i];
+        (ok ? lz : rest).push_back(i);
+    }
+    auto larger = [&](int64_t a, int64_t b) { return n[a] > n[b]; };
+    std::stable_sort(lz.begin(), lz.end(), larger);
+    std::stable_sort(rest.begin(), rest.end(), larger);
+    if (!lz.empty())
+        TRY(solve_batched_lz(ctx, lz, n, s, A, lda, B, ldb, o, Lambda, X, ldx, nstreams, status, infos));
+    if (!rest.empty()) {
+        TRY(run_workers(ctx, nstreams, (int64_t)rest.size(), [&](gsyeig_ctx *w, int64_t k) {
+            const int64_t i = rest[k];
+            gsyeig_info inf;
+            memset(&inf, 0, sizeof(inf));
+            status[i] = gsyeig_solve(w, n[i], s[i], A[i], lda[i], B[i], ldb[i], &o, Lambda[i], X[i], ldx[i], &inf);
+            if (infos) infos[i] = inf;
+            return 0;
+        }));
+    }
     for (int64_t i = 0; i < count; ++i)
         if (status[i]) return status[i];
     return 0;

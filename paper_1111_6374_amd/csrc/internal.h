@@ -71,6 +71,7 @@ enum WsSlot {
     WS_TRSVQ,      // work queues and sentinel partial buffers of the queue sweeps
     WS_CKE,        // variant KE: the explicit C = U^-T A U^-1 (n x n FP64)
     WS_CKE2,       // variant KE: the second n x n buffer of its formation
+    WS_BATCH,      // batched Lanczos phase: every instance's factor data, basis and state
     WS_COUNT
 };
 
@@ -253,6 +254,35 @@ int lz_z0_parts(int64_t n);
 // queue ticket, workgroups done, sticky wait-expiry flag, spin bound (0 =
 // SPIN_LIMIT), phase counters; zero between launches (the last workgroup
 // resets it).
+// Batched Lanczos phase (k_lzb.hip): one workgroup per instance, n <= LZB_NMAX.
+#define LZB_NMAX 4096
+struct LzbDesc {
+    // problem and operator (rows contiguous: element (r, c) at M[r * ld + c])
+    int64_t n, s, nvec, mmax, every;
+    int which;
+    double tol;
+    const void *U; int64_t ldu;   // Cholesky factor, upper triangle (float or double)
+    const double *Dinv;           // FP64 inverses of U's 64 x 64 diagonal blocks
+    const void *A; int64_t lda;   // symmetric A, upper triangle read (float or double)
+    uint64_t seed;                // start vector w_0 = SplitMix64(seed), normalised
+    // Lanczos data
+    double *V; int64_t ldv;       // w_0 .. w_m, column j at V + j * ldv
+    double *alpha, *beta;         // mmax each
+    double *om; int64_t ldom;     // three omega columns of ldom >= mmax + 2
+    double *chk;                  // lzb_scratch_doubles(n, mmax) doubles
+    // state kept between launches (zero before the first)
+    int64_t k, next_check, prev_m;
+    double prev_rho, anorm;
+    int forced, reorth_steps;
+    int status;                   // 0 running; 1 the pre-check passed on all s wanted
+                                  // values; 2 on the innermost ones (full check due);
+                                  // 3 the step cap mmax was reached; 4 the basis lost
+                                  // orthogonality (Gram-Schmidt lengthened z)
+    int64_t ticks;                // device wall-clock ticks (100 MHz) spent
+};
+int64_t lzb_scratch_doubles(int64_t n, int64_t mmax);
+int launch_lzb(LzbDesc *desc, const int *order, int count, unsigned *next, int f32, hipStream_t st);
+
 struct LzCtl {
     unsigned ticket, done, err, spin;
     unsigned ph[12];

@@ -336,6 +336,7 @@ def test_mixed_batched_equals_single(gs, torch):
     insts = [gen.known_spectrum(n, seed=gen.BASE_SEED, stream=(44, i)) for i, n in enumerate(sizes)]
     o = gs.gsyeig_opts_default()
     o.prec = gs.GSYEIG_MIXED
+    o.batch_mode = 1  # each instance a gsyeig_solve: bit for bit
     A = [dev(torch, d["A"]) for d in insts]
     B = [dev(torch, d["B"]) for d in insts]
     Lam = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in ss]
