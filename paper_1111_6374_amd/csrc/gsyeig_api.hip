@@ -1200,13 +1200,16 @@ static int64_t batch_ld(int64_t n)
     return (ld % 512 == 0) ? ld + 64 : ld;
 }
 
-// The batched Lanczos kernel reads rows with 16-byte loads that may run past
-// column n - 1 into the row's padding: a caller's FP64 matrix is read in
-// place when its base is 16-byte aligned, rows are an even number of
-// doubles (not a multiple of 512) and n is even; otherwise from a copy.
+// The batched Lanczos kernel reads rows with 16-byte buffer loads that may
+// run past column n - 1 into the row's padding, through a resource whose
+// extent (n rows of ld elements) stays below 2^31 bytes: a caller's FP64
+// matrix is read in place when its base is 16-byte aligned, rows are an even
+// number of doubles (not a multiple of 512), n is even and the extent fits;
+// otherwise from a copy.
 static bool aligned16(const double *p, int64_t ld, int64_t n)
 {
-    return ((uintptr_t)p % 16 == 0) && (ld % 2 == 0) && (ld % 512 != 0) && (n % 2 == 0);
+    return ((uintptr_t)p % 16 == 0) && (ld % 2 == 0) && (ld % 512 != 0) && (n % 2 == 0) &&
+           n * ld * (int64_t)sizeof(double) < ((int64_t)1 << 31);
 }
 
 // One instance's device data in the batch pool.

@@ -118,8 +118,8 @@ __device__ __forceinline__ double ld(const T *p)
     return (double)ldr(p);
 }
 
-// 16-byte loads: VW consecutive elements (4 FP32, 2 FP64) at a 16-byte
-// aligned address; elements at or past `lim` (the row's end) read as 0.
+// 16-byte groups: VW consecutive elements (4 FP32, 2 FP64) at a 16-byte
+// aligned address.
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec;
@@ -131,10 +131,44 @@ template <> struct Vec<double> {
     using type = d2v;
     static constexpr int n = 2;
 };
+
+// Matrix rows are read with buffer loads: the matrix's base and extent sit
+// in a scalar resource, the row's byte offset is a scalar and a thread adds
+// only its 32-bit column offset.  A per-thread 64-bit address per column
+// group, live across the loops, does not fit the register budget of a
+// 1024-thread workgroup; spilled, each of its reloads waits for every load
+// in flight, and the stages' loads no longer overlap.  The matrix's bytes
+// (n rows of ld elements) must stay below 2^31.
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+struct Mat {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t pitch;  // bytes per row
+};
 template <typename T>
-__device__ __forceinline__ typename Vec<T>::type ldvec(const T *p)
+__device__ __forceinline__ Mat mat(const T *p, int64_t ld, int64_t n)
 {
-    return *(const GAS typename Vec<T>::type *)p;
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    Mat m;
+    m.pitch = __builtin_amdgcn_readfirstlane((uint32_t)(ld * (int64_t)sizeof(T)));
+    const uint32_t bytes = __builtin_amdgcn_readfirstlane((uint32_t)(n * ld * (int64_t)sizeof(T)));
+    // word 3: 32-bit data format, the raw layout of CDNA buffer resources
+    m.rs = __builtin_amdgcn_make_buffer_rsrc((void *)((uint64_t)hi << 32 | lo), (short)0, (int)bytes, 0x00020000);
+    return m;
+}
+// VW elements of row r from column c (16-byte aligned), or zeros where ok
+// is false: the column offset then lies past the resource's extent, and a
+// buffer load out of range returns zeros without touching memory.  Every
+// lane issues the load, so no branch splits a stage, and the wait for one
+// stage's data leaves the next stage's loads in flight (a load skipped on
+// some path would make that wait count every load).
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::type ldrow(const Mat &m, int r, int c, bool ok)
+{
+    const unsigned voff = ok ? (unsigned)c * (unsigned)sizeof(T) : 0x80000000u;
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(m.rs, voff, (unsigned)r * m.pitch, 0);
+    return __builtin_bit_cast(typename Vec<T>::type, v);
 }
 
 // Every load of the three operator passes reads matrix entries only; the
@@ -146,8 +180,7 @@ __device__ __forceinline__ typename Vec<T>::type ldvec(const T *p)
 // tile i take their dot products with the solved tail (a wave per four rows,
 // each lane VW consecutive columns per load), then x_i = Dinv_i t.
 template <typename T>
-__device__ void sweep_u(const T *__restrict__ U, int64_t ldu, const double *__restrict__ Dinv, int64_t n,
-                        Lds &L)
+__device__ void sweep_u(const Mat &U, const double *__restrict__ Dinv, int64_t n, Lds &L)
 {
     using VT = typename Vec<T>::type;
     constexpr int VW = Vec<T>::n, SPAN = 64 * VW, UB = 2;
@@ -156,16 +189,18 @@ __device__ void sweep_u(const T *__restrict__ U, int64_t ldu, const double *__re
     const int nn = (int)n;
     const int nt = (nn + 63) / 64;
     // stage (tile t, first column c): rows 64 t + 4 w + j (clamped to the
-    // tile), columns c + SPAN e .. + VW - 1; zero past n
-    auto stage = [&](int t, int c, VT u[UB][4]) {
+    // tile), columns c + SPAN e .. + VW - 1; zero past n, and all zero
+    // unless live (the stages past a tile's end and before tile 0 are
+    // issued too, as zeros, so that no branch splits the pipeline)
+    auto stage = [&](int t, int c, VT u[UB][4], bool live) {
         const int rt = nn - 64 * t < 64 ? nn - 64 * t : 64;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const T *Ur = U + (int64_t)(64 * t + ((4 * w + j) < rt ? 4 * w + j : rt - 1)) * ldu;
+            const int r = 64 * t + ((4 * w + j) < rt ? 4 * w + j : rt - 1);
 #pragma unroll
             for (int e = 0; e < UB; ++e) {
                 const int ce = c + SPAN * e;
-                u[e][j] = (ce < nn) ? ldvec(Ur + ce) : (VT)0;
+                u[e][j] = ldrow<T>(U, r, ce, live && ce < nn);
             }
         }
     };
@@ -186,7 +221,7 @@ __device__ void sweep_u(const T *__restrict__ U, int64_t ldu, const double *__re
             }
     };
     VT ua[UB][4], ub[UB][4];
-    stage(nt - 1, 64 * nt + VW * lane, ua);
+    stage(nt - 1, 64 * nt + VW * lane, ua, true);
     for (int ti = nt - 1; ti >= 0; --ti) {
         const int r0 = ti * 64;
         const int rows = (nn - r0) < 64 ? (nn - r0) : 64;
@@ -201,15 +236,16 @@ __device__ void sweep_u(const T *__restrict__ U, int64_t ldu, const double *__re
         const int ns = nstages(ti);
         const int cb = r0 + 64 + VW * lane;
         for (int st = 0;; st += 2) {
-            if (st + 1 < ns) stage(ti, cb + (st + 1) * UB * SPAN, ub);
+            // past the tile's last stage the columns are past n: zeros
+            stage(ti, cb + (st + 1) * UB * SPAN, ub, true);
             dot(ua, cb + st * UB * SPAN, acc);
             if (st + 1 >= ns) break;
-            if (st + 2 < ns) stage(ti, cb + (st + 2) * UB * SPAN, ua);
+            stage(ti, cb + (st + 2) * UB * SPAN, ua, true);
             dot(ub, cb + (st + 1) * UB * SPAN, acc);
             if (st + 2 >= ns) break;
         }
         // the next tile's first stage, in flight across this tile's barriers
-        if (ti > 0) stage(ti - 1, r0 + VW * lane, ua);
+        stage(ti > 0 ? ti - 1 : 0, r0 + VW * lane, ua, ti > 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = wsum(acc[j]);
         if (lane == 0) {
@@ -251,8 +287,7 @@ __device__ __forceinline__ int owned_col(int tid, int q)
 // symmetric only to FP64 rounding can differ from its transpose by an FP32
 // ulp once rounded to FP32, which the Lanczos recurrence does not tolerate.
 template <typename T>
-__device__ void symv_upper(const T *__restrict__ A, int64_t lda, int64_t n, const double *xv, double *P,
-                           double y[CPT])
+__device__ void symv_upper(const Mat &A, int64_t n, const double *xv, double *P, double y[CPT])
 {
     using VT = typename Vec<T>::type;
     constexpr int VW = Vec<T>::n, NQ = CPT / VW, RG = 4;
@@ -268,20 +303,21 @@ __device__ void symv_upper(const T *__restrict__ A, int64_t lda, int64_t n, cons
             y[q * VW + v] = 0.0;
             xq[q * VW + v] = (c < nn) ? xv[c] : 0.0;
         }
-    // rows r0 .. r0 + RG - 1 (clamped to n - 1) at the owned column groups
-    // that reach the diagonal; zero elsewhere
+    // rows r0 .. r0 + RG - 1 at the owned column groups that reach the
+    // diagonal; zero elsewhere and past row n - 1
     auto stage = [&](int r0, VT a[RG][NQ]) {
 #pragma unroll
         for (int e = 0; e < RG; ++e) {
             const int r = r0 + e;
-            const T *Ar = A + (int64_t)(r < nn ? r : nn - 1) * lda;
+            const int rr = r < nn ? r : nn - 1;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int c = owned_col<T>(tid, q);
-                a[e][q] = (c < nn && c + VW - 1 >= r) ? ldvec(Ar + c) : (VT)0;
+                a[e][q] = ldrow<T>(A, rr, c, r < nn && c < nn && c + VW - 1 >= r);
             }
         }
     };
+    double pacc = 0.0;
     auto group = [&](const VT a[RG][NQ], int r0) {
         double pr[RG];
 #pragma unroll
@@ -312,16 +348,24 @@ __device__ void symv_upper(const T *__restrict__ A, int64_t lda, int64_t n, cons
         h1 += __shfl_xor(h1, 4);
         h1 += __shfl_xor(h1, 2);
         h1 += __shfl_xor(h1, 1);
-        const int e = (b5 ? 2 : 0) + (b4 ? 1 : 0);
-        if ((lane & 15) == 0 && r0 + e < nn) gpw(P)[w * nn + r0 + e] = h1;
+        // row r0 + e's sum is in the lanes 16 e .. 16 e + 15; lane l keeps
+        // row 64 floor(r0 / 64) + l and the wave stores its 64 rows at once
+        const double hv = __shfl(h1, 16 * (lane & 3));
+        if ((lane >> 2) == ((r0 & 63) >> 2)) pacc = hv;
+        if ((r0 & 63) == 64 - RG || r0 + RG >= nn) {
+            const int rb = r0 & ~63;
+            if (rb + lane < nn) gpw(P)[w * nn + rb + lane] = pacc;
+        }
     };
+    // every stage is issued (as zeros past row n - 1), so that no branch
+    // splits the pipeline
     VT ga[RG][NQ], gb[RG][NQ];
     stage(0, ga);
     for (int r0 = 0;; r0 += 2 * RG) {
-        if (r0 + RG < nn) stage(r0 + RG, gb);
+        stage(r0 + RG, gb);
         group(ga, r0);
         if (r0 + RG >= nn) break;
-        if (r0 + 2 * RG < nn) stage(r0 + 2 * RG, ga);
+        stage(r0 + 2 * RG, ga);
         group(gb, r0 + RG);
         if (r0 + 2 * RG >= nn) break;
     }
@@ -348,26 +392,27 @@ __device__ void symv_upper(const T *__restrict__ A, int64_t lda, int64_t n, cons
 // then every owner of a later column subtracts tile i's rows times z_i,
 // eight rows per stage.
 template <typename T>
-__device__ void sweep_ut(const T *__restrict__ U, int64_t ldu, const double *__restrict__ Dinv, int64_t n,
-                         double y[CPT], Lds &L)
+__device__ void sweep_ut(const Mat &U, const double *__restrict__ Dinv, int64_t n, double y[CPT], Lds &L)
 {
     using VT = typename Vec<T>::type;
     constexpr int VW = Vec<T>::n, NQ = CPT / VW, RR = (sizeof(T) == 4) ? 8 : 4;
+    constexpr int NG = 64 / RR;  // stages per tile (even)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nn = (int)n;
     const int nt = (nn + 63) / 64;
-    // stage (tile t, rows 64 t + 8 g ..): the owned column groups right of
-    // the tile; rows past n read row n - 1 (their z is 0)
+    // stage (tile t, rows 64 t + RR g ..): the owned column groups right of
+    // the tile; zero for rows past n - 1 (their z is 0) and for g past the
+    // tile's last stage (issued too, so that no branch splits the pipeline)
     auto stage = [&](int t, int g, VT u[RR][NQ]) {
 #pragma unroll
         for (int e = 0; e < RR; ++e) {
             const int r = 64 * t + RR * g + e;
-            const T *Ur = U + (int64_t)(r < nn ? r : nn - 1) * ldu;
+            const int rr = r < nn ? r : nn - 1;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int c = owned_col<T>(tid, q);
-                u[e][q] = (c >= 64 * t + 64 && c < nn) ? ldvec(Ur + c) : (VT)0;
+                u[e][q] = ldrow<T>(U, rr, c, g < NG && r < nn && c >= 64 * t + 64 && c < nn);
             }
         }
     };
@@ -381,7 +426,6 @@ __device__ void sweep_ut(const T *__restrict__ U, int64_t ldu, const double *__r
                 for (int v = 0; v < VW; ++v) y[q * VW + v] = fma(-(double)u[e][q][v], zr, y[q * VW + v]);
         }
     };
-    constexpr int NG = 64 / RR;  // stages per tile (even)
     VT pa[RR][NQ], pb[RR][NQ];
     for (int ti = 0; ti < nt; ++ti) {
         const int r0 = ti * 64;
@@ -417,7 +461,7 @@ __device__ void sweep_ut(const T *__restrict__ U, int64_t ldu, const double *__r
         for (int g = 0; g < NG; g += 2) {
             stage(ti, g + 1, pb);
             panel(pa, r0 + RR * g);
-            if (g + 2 < NG) stage(ti, g + 2, pa);
+            stage(ti, g + 2, pa);
             panel(pb, r0 + RR * (g + 1));
         }
     }
@@ -493,8 +537,8 @@ __device__ void run_instance(LzbDesc &d, Lds &L)
     const int tid = threadIdx.x;
     const uint64_t t0 = wall_clock64();
     const int64_t n = d.n, mmax = d.mmax, every = d.every, s = d.s, ldv = d.ldv;
-    const T *U = (const T *)d.U;
-    const T *A = (const T *)d.A;
+    const Mat U = mat((const T *)d.U, d.ldu, n);
+    const Mat A = mat((const T *)d.A, d.lda, n);
     double *V = d.V, *alpha = d.alpha, *beta = d.beta, *om = d.om;
     const int64_t ldom = d.ldom;
     double *P = d.chk;                         // NW x n row sums of the product with A
@@ -533,10 +577,10 @@ __device__ void run_instance(LzbDesc &d, Lds &L)
         for (int64_t i = tid; i < n; i += NT) L.x[i] = L.wk[i];
         if (tid < 4 && n + tid < NMX) L.x[n + tid] = 0.0;
         __syncthreads();
-        sweep_u<T>(U, d.ldu, d.Dinv, n, L);
+        sweep_u<T>(U, d.Dinv, n, L);
         double y[CPT];
-        symv_upper<T>(A, d.lda, n, L.x, P, y);
-        sweep_ut<T>(U, d.ldu, d.Dinv, n, y, L);
+        symv_upper<T>(A, n, L.x, P, y);
+        sweep_ut<T>(U, d.Dinv, n, y, L);
         // KI4: alpha_k, beta_k, the omega recurrence, w_{k+1}
         double *omC = om + (k % 3) * ldom, *omN = om + ((k + 1) % 3) * ldom;
         const double *omP = om + ((k + 2) % 3) * ldom;
@@ -705,7 +749,7 @@ __global__ __launch_bounds__(1024) void k_lzb(LzbDesc *desc, const int *order, i
             L.inst = (q < (unsigned)count) ? order[q] : -1;
         }
         __syncthreads();
-        const int i = L.inst;
+        const int i = __builtin_amdgcn_readfirstlane(L.inst);
         __syncthreads();
         if (i < 0) break;
         run_instance<T>(desc[i], L);
