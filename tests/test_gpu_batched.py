@@ -147,3 +147,49 @@ def test_batched_one_launch_fp64_instance_that_loses_orthogonality():
     lam = np.sort(d["lam"])[:s]
     assert np.max(np.abs(Lam.cpu().numpy() - lam)) <= 1e-10 * np.max(np.abs(d["lam"]))
     assert infos[0].eta_max <= 1e-12
+
+
+def test_batched_one_launch_fp64_wide_rows_read_from_a_copy():
+    """FP64 matrices whose n rows span more than 2^31 bytes (leading
+    dimension 2^22 + 2, n = 64): the one-launch phase addresses rows through
+    32-bit buffer offsets, so such a caller's A and factor are read from
+    copies in the batch pool rather than in place.  The result equals the
+    same instance given with ld = n (read in place) and meets the known-
+    spectrum bar."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1111_6374_amd as gs
+
+    n, ld = 64, (1 << 22) + 2
+    s = math.ceil(0.05 * n)
+    d = gen.known_spectrum(n, seed=gen.BASE_SEED + 4, stream=(4, 9001))
+    say("batched one-launch, wide rows", n, ld, s)
+    o = gs.gsyeig_opts_default()
+    o.prec = gs.GSYEIG_FP64
+    res = []
+    for ldm in (n, ld):
+        A = torch.zeros(n, ldm, dtype=torch.float64, device="cuda")
+        B = torch.zeros(n, ldm, dtype=torch.float64, device="cuda")
+        A[:, :n] = torch.from_numpy(d["A"]).cuda()
+        B[:, :n] = torch.from_numpy(d["B"]).cuda()
+        Lam = torch.zeros(s, dtype=torch.float64, device="cuda")
+        X = torch.zeros(s, n, dtype=torch.float64, device="cuda")
+        with gs.Solver() as sv:
+            rc, status, infos = gs.gsyeig_solve_batched(sv.ctx, [n], [s], [A], [ldm], [B], [ldm], o, [Lam], [X], [n],
+                                                        nstreams=1)
+        torch.cuda.synchronize()
+        assert rc == 0 and status[0] == 0, (ldm, rc, status)
+        assert infos[0].eta_max <= 1e-12
+        res.append((Lam.cpu().numpy(), X.cpu().numpy()))
+        del A, B
+    lam = np.sort(d["lam"])[:s]
+    scale = np.max(np.abs(d["lam"]))
+    for L, _ in res:
+        assert np.max(np.abs(L - lam)) <= 1e-10 * scale
+    assert np.max(np.abs(res[0][0] - res[1][0])) <= 1e-12 * scale
+    # same vectors up to sign
+    for i in range(s):
+        a, b = res[0][1][i], res[1][1][i]
+        sg = 1.0 if np.dot(a, b) >= 0 else -1.0
+        assert np.max(np.abs(a - sg * b)) <= 1e-8 * np.max(np.abs(a))
