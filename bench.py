@@ -961,6 +961,14 @@ def bench_batched(args, cfg):
         "batched_per_instance_solves_s": t_mode1,
         "lanczos_one_launch_ms_sum": float(sum(i.t_ki_ms for i in infos)),
         "lanczos_steps_total": int(sum(i.steps for i in infos)),
+        # bytes the Lanczos operator reads and writes per step, summed over the
+        # steps: A's upper triangle and U's twice (n (n + 1) / 2 elements each,
+        # FP32 mixed / FP64), the 64 x 64 FP64 diagonal-block inverses twice
+        # (64 n doubles each time) and the product's row-sum scratch written
+        # and read once (16 n doubles each way)
+        "lanczos_operator_bytes": float(sum(i.steps * (3 * n * (n + 1) // 2 * (4 if prec == gs.GSYEIG_MIXED else 8)
+                                                       + 2 * 64 * n * 8 + 2 * 16 * n * 8)
+                                            for i, n in zip(infos, sizes))),
         "parity": {"e_lambda_vs_known": e_lam, "eta_max": eta, "pass": bool(e_lam <= 1e-10 and eta <= 1e-10)},
     }
     solver.close()
