@@ -257,7 +257,9 @@ int lz_z0_parts(int64_t n);
 // Batched Lanczos phase (k_lzb.hip): one workgroup per instance, n <= LZB_NMAX.
 #define LZB_NMAX 4096
 struct LzbDesc {
-    // problem and operator (rows contiguous: element (r, c) at M[r * ld + c])
+    // problem and operator (rows contiguous: element (r, c) at M[r * ld + c];
+    // U and A 16-byte aligned, ld even, n rows of ld elements below 2^31
+    // bytes: the kernel reads them through 32-bit buffer offsets)
     int64_t n, s, nvec, mmax, every;
     int which;
     double tol;
